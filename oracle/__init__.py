@@ -1,0 +1,25 @@
+"""CPU FP64 oracle for the corrector systems of the one-domain
+Navier-Stokes-Brinkman solver (Arico, Helmig, Puleo, Schneider,
+arXiv 2309.03543).
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or
+execute this package; only the test suite, the smoke check and the CPU
+baseline leg of the benchmark use it.  It is a plain, slow, obviously correct
+restatement of what the paper defines, written in NumPy/SciPy in float64,
+and shares no code with the GPU library.
+
+Modules
+  geometry   per-cell geometry, side pairing, transmissibilities (Sec. 3.2.2,
+             eq. cs1_discr; Appendix A side numbering)
+  ordering   reverse Cuthill-McKee renumbering and the CSR pattern
+  assemble   cell tensors and the CP1 / CP2 matrices (eq. CS1_sys_coeff,
+             eq. Cs2_4, eq. CS2_sys_coeff)
+  pcg        Jacobi-preconditioned conjugate gradients with residual
+             replacement; dense Cholesky reference (Sec. 3.2.2-3.2.3)
+  adjoint    adjoint solve and parameter gradients (derived from the
+             symmetric corrector systems)
+
+Parity status: every function above is pinned by tests/test_oracle_*.py
+against closed forms, invariants, special cases or brute force; none is
+"parity unpinned".
+"""

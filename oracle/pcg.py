@@ -1,0 +1,116 @@
+"""Oracle: preconditioned conjugate gradients and a dense reference solve.
+
+TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
+
+The paper solves both corrector systems with PCG (Sec. 3.2.2, after
+eq. CS1_sys_coeff; Sec. 3.2.3, after eq. CS2_sys_coeff, citing
+Hestenes-Stiefel).  Its incomplete-Cholesky preconditioner is replaced by the
+diagonal (Jacobi) one, which needs no sequential triangular sweeps.
+
+The paper states no tolerance.  The solver is specified as follows (the same
+specification the GPU library implements):
+
+  x = x0, x_acc = 0, r = b - A x (true residual), z = D^{-1} r, p = z,
+  rho = r.z
+  iteration k = 1, 2, ...:
+    q = A p; alpha = rho / (p.q)   (breakdown if p.q <= 0 or not finite)
+    x_acc += alpha p; r -= alpha q
+    if k is a multiple of m:
+        x += x_acc; x_acc = 0                     (group update)
+        r = b - A x   (true residual, correctly rounded)
+        stop if ||r||_2 <= tol * ||b||_2
+    z = D^{-1} r; rho' = r.z; p = z + (rho'/rho) p; rho = rho'
+
+Two details are what make 1e-10 reachable on these matrices, whose
+transmissibilities span several decades: the increments are summed in a
+separate vector and folded into x only at replacement points (group update),
+and the true residual is evaluated exactly and then rounded, so the stopping
+test measures the iterate rather than the rounding of the check itself.  Here
+the residual is evaluated in x87 extended precision (64-bit significand),
+whose error is far below one float64 ulp of the result for these row lengths.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+
+OK, MAXIT, BREAKDOWN = 0, 1, -6
+
+
+def true_residual(A, b, x) -> np.ndarray:
+    """b - A x evaluated in extended precision and rounded to float64."""
+    ld = np.longdouble
+    prod = A.data.astype(ld) * np.asarray(x, np.float64).astype(ld)[A.indices]
+    if np.all(np.diff(A.indptr) > 0):
+        s = np.add.reduceat(prod, A.indptr[:-1])
+    else:
+        rows = np.repeat(np.arange(A.shape[0]), np.diff(A.indptr))
+        s = np.zeros(A.shape[0], ld)
+        np.add.at(s, rows, prod)
+    return (np.asarray(b, np.float64).astype(ld) - s).astype(np.float64)
+
+
+def pcg(A, b, tol=1e-10, max_it=100000, replace_every=50, x0=None, record=False) -> tuple:
+    """Jacobi PCG with group-update residual replacement every `replace_every`
+    iterations; returns (x, info) with info = iters, status, rel_res_true."""
+    b = np.asarray(b, np.float64)
+    n = b.shape[0]
+    x = np.zeros(n) if x0 is None else np.array(x0, np.float64)
+    bnorm = float(np.linalg.norm(b))
+    info = {"iters": 0, "status": OK, "rel_res_true": 0.0, "history": []}
+    if bnorm == 0.0:
+        return np.zeros(n), info
+    dinv = 1.0 / A.diagonal()
+    r = true_residual(A, b, x)
+    res = float(np.linalg.norm(r)) / bnorm
+    info["rel_res_true"] = res
+    if res <= tol:
+        return x, info
+    xacc = np.zeros(n)
+    z = dinv * r
+    p = z.copy()
+    rho = float(r @ z)
+    k = 0
+    while k < max_it:
+        q = A @ p
+        pq = float(p @ q)
+        if not (pq > 0.0) or not np.isfinite(pq):
+            info["status"] = BREAKDOWN
+            break
+        alpha = rho / pq
+        xacc += alpha * p
+        r -= alpha * q
+        k += 1
+        if k % replace_every == 0:
+            x += xacc
+            xacc[:] = 0.0
+            r = true_residual(A, b, x)
+            res = float(np.linalg.norm(r)) / bnorm
+            if record:
+                info["history"].append((k, res))
+            if res <= tol:
+                info.update(iters=k, rel_res_true=res)
+                return x, info
+        z = dinv * r
+        rho_new = float(r @ z)
+        p = z + (rho_new / rho) * p
+        rho = rho_new
+    x += xacc
+    info["iters"] = k
+    info["rel_res_true"] = float(np.linalg.norm(true_residual(A, b, x))) / bnorm
+    if info["status"] == OK:
+        info["status"] = MAXIT
+    return x, info
+
+
+def rel_residual(A, b, x) -> float:
+    """||b - A x||_2 / ||b||_2 with the residual evaluated as in pcg()."""
+    bn = float(np.linalg.norm(b))
+    return float(np.linalg.norm(true_residual(A, b, x))) / bn if bn > 0 else 0.0
+
+
+def dense_solve(A, b) -> np.ndarray:
+    """Direct solve by dense Cholesky (small systems only)."""
+    M = A.toarray() if hasattr(A, "toarray") else np.asarray(A)
+    c = sla.cho_factor(M, lower=True)
+    return sla.cho_solve(c, np.asarray(b, np.float64))
