@@ -1,0 +1,268 @@
+/*
+ * pmcorr — corrector-system PCG for the mesoscopic one-domain
+ * Navier-Stokes-Brinkman solver of Arico, Helmig, Puleo and Schneider
+ * (arXiv 2309.03543), on AMD Instinct MI355X (gfx950).
+ *
+ * The two corrector problems of the fractional time step (Sec. 3.1, eq. cs1
+ * and eq. cs2) reduce, per time step, to sparse symmetric positive definite
+ * M-matrix systems on an unstructured Delaunay triangulation, one unknown per
+ * triangle (Sec. 3.2.2, eq. CS1_sys_coeff; Sec. 3.2.3, eq. CS2_sys_coeff).
+ * This library builds their sparsity once per mesh, assembles their values
+ * from per-cell porosity and permeability on the GPU, and solves them with
+ * Jacobi-preconditioned conjugate gradients on the GPU.
+ *
+ * Conventions shared by every entry point
+ *   - Triangles are given counter-clockwise; side j of triangle e is the side
+ *     opposite node j, i.e. from node (j+1)%3 to node (j+2)%3 (Appendix A).
+ *   - side_tag[e*3+j] is a bit mask for boundary sides: bit 0 marks a Dirichlet
+ *     side of CP1, bit 1 a Dirichlet side of CP2.  Untagged boundary sides are
+ *     Neumann (no matrix term).  Tags on interior sides are ignored.
+ *   - Public vectors (right-hand sides, solutions, per-cell parameters,
+ *     gradients) are indexed by the caller's cell order.  Matrices are CSR
+ *     with rows and columns in the library's reverse Cuthill-McKee order,
+ *     which pm_mesh_export / pm_structure_host reveal (perm[new] = old).
+ *   - Device pointers are owned by the caller; the library never frees them.
+ *     Handles (pm_mesh, pm_batch) own their device workspace, freed by the
+ *     matching *_destroy.  Calls on one handle must not overlap in time.
+ *   - Every call returns a status (PM_OK = 0, > 0 warnings, < 0 errors) and
+ *     never throws.  Work is ordered on the caller's HIP stream; calls that
+ *     report solver information (pcg_*) block the host until it is known.
+ */
+#ifndef PMCORR_H
+#define PMCORR_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define PM_OK 0
+#define PM_MAXIT 1          /* iteration limit reached before the tolerance */
+#define PM_STAGNATED 2      /* the true residual stopped decreasing near the float64
+                               rounding floor of the system, which lies above tol */
+#define PM_INVALID_ARG (-1) /* bad sizes, null pointers, out-of-range indices or tags */
+#define PM_BAD_MESH (-2)    /* clockwise/degenerate triangle, repeated node, non-manifold side */
+#define PM_NOT_DELAUNAY (-3) /* interior side with d <= 0, or Dirichlet side whose
+                                circumcenter-to-side distance is <= 0 */
+#define PM_SINGULAR (-4)    /* CP2 on a mesh component without a CP2 Dirichlet side */
+#define PM_NONFINITE (-5)   /* NaN/Inf in coordinates, parameters, matrix or right-hand side */
+#define PM_BREAKDOWN (-6)   /* p.Ap <= 0 or not finite during PCG */
+#define PM_HIP_ERROR (-7)   /* a HIP runtime call failed (message via pm_last_error) */
+
+/* corrector kinds */
+#define PM_CP1X 0 /* eq. CS1_sys_coeff, x component: diagonal M11*A_e + nu*sum l/d */
+#define PM_CP1Y 1 /* eq. CS1_sys_coeff, y component: diagonal M22*A_e + nu*sum l/d */
+#define PM_CP2 2  /* eq. CS2_sys_coeff: coefficients (l/d) * (Xi_j n_j).n_j */
+
+/* precisions */
+#define PM_FP64 0  /* all vectors and the matrix in float64 */
+#define PM_MIXED 1 /* float32 matrix and Krylov vectors; float64 solution,
+                      residual replacement and convergence test */
+
+typedef struct pm_mesh pm_mesh;
+typedef struct pm_batch pm_batch;
+
+typedef struct {
+  int32_t n_cells;
+  int32_t n_nodes;
+  int32_t nnz;              /* n_cells + 2 * n_interior_sides */
+  int32_t n_interior_sides;
+  int32_t n_boundary_sides;
+  int32_t bandwidth;        /* max |row - col| in the renumbered matrix */
+  int32_t n_components;     /* connected components of the cell graph */
+  int32_t index_bits;       /* 16 or 32: width of the column offsets the solver streams */
+  double max_T;             /* largest transmissibility l/d */
+  double min_cot_sum;       /* smallest cot(t_e)+cot(t_ep) over interior sides */
+} pm_mesh_stats;
+
+/*
+ * Per-cell coefficients, device pointers of length n_cells in cell order.
+ *   eps   porosity (> 0)
+ *   logk  s = ln K, natural log of the permeability scale
+ *   chi   transition factor in [0,1] multiplying the inverse permeability;
+ *         NULL means 1
+ *   g11, g12, g22  normalised inverse-shape tensor G (symmetric positive
+ *         definite); NULL means identity.  Inverse permeability
+ *         Kfrak = chi * exp(-s) * G (Sec. 2: Kfrak = K^{-1}; eq. aniso gives
+ *         G = R diag(beta,1) R^T).
+ */
+typedef struct {
+  const double* eps;
+  const double* logk;
+  const double* chi;
+  const double* g11;
+  const double* g12;
+  const double* g22;
+} pm_cell_params;
+
+typedef struct {
+  double tol;            /* stop when ||b - A x||_2 <= tol * ||b||_2 (default 1e-10) */
+  int32_t max_it;        /* iteration limit (default 200000) */
+  int32_t precision;     /* PM_FP64 or PM_MIXED */
+  int32_t replace_every; /* true-residual replacement period m (default 50); the
+                            stopping test runs at these points */
+  int32_t x0_is_zero;    /* 1: ignore x on entry and start from 0 */
+  int32_t block;         /* threads per block for the iteration kernels; 0 = tuned */
+  int32_t grid;          /* blocks for the iteration kernels; 0 = tuned */
+  int32_t stag_checks;   /* replacement points without the residual halving, once
+                            below 1000*max(tol*||b||, u*|| |A||x| ||), before
+                            PM_STAGNATED (default 40) */
+} pm_opts;
+
+typedef struct {
+  int32_t iters;         /* PCG iterations performed */
+  int32_t status;        /* PM_OK, PM_MAXIT, PM_STAGNATED or an error */
+  double rel_res_true;   /* ||b - A x||_2 / ||b||_2 of the returned x, residual
+                            evaluated with error-free transformations (exact
+                            up to the final rounding) */
+  double bnorm;          /* ||b||_2 */
+} pm_info;
+
+/* Defaults for pm_opts (tol 1e-10, FP64, m = 50, x0 = 0, tuned launch). */
+void pm_opts_default(pm_opts* opts);
+
+/* Human-readable name of a status code. */
+const char* pm_status_string(int status);
+
+/* Copies the message of the last failing call on this thread into buf
+ * (NUL-terminated, truncated to len) and returns its status. */
+int pm_last_error(char* buf, int32_t len);
+
+/*
+ * Host-only mesh analysis (no GPU needed): validation, per-side
+ * transmissibilities, reverse Cuthill-McKee order and the CSR pattern.
+ *   xy       [n_nodes][2] host float64 node coordinates
+ *   tri      [n_cells][3] host int32 CCW node indices
+ *   side_tag [n_cells][3] host int8 boundary bit masks (see above)
+ *   perm     [n_cells] out: perm[new] = old
+ *   row_ptr  [n_cells+1] out, col [col_capacity] out (needs nnz <= col_capacity;
+ *            4*n_cells always suffices)
+ *   T        [n_cells][3] out, nullable: l/d per side in cell order (interior:
+ *            2/(cot t_e + cot t_ep); boundary: 2/cot t; 0 where cot t <= 0)
+ *   stats    out, nullable
+ * Geometry follows Sec. 3.2.2 (eq. cs1_discr, d = signed circumcenter
+ * distance) using the identity d = (l/2)(cot t_e + cot t_ep).
+ * Errors: PM_INVALID_ARG, PM_NONFINITE, PM_BAD_MESH, PM_NOT_DELAUNAY.
+ */
+int pm_structure_host(int32_t n_nodes, const double* xy, int32_t n_cells, const int32_t* tri,
+                      const int8_t* side_tag, int32_t* perm, int32_t* row_ptr, int32_t* col,
+                      int32_t col_capacity, double* T, pm_mesh_stats* stats);
+
+/*
+ * Builds the mesh structure (as pm_structure_host) and uploads it with the
+ * solver workspace to the current HIP device.  Inputs are host arrays and
+ * are not retained.  *out receives a handle owned by the caller.
+ */
+int pm_mesh_create(int32_t n_nodes, const double* xy, int32_t n_cells, const int32_t* tri,
+                   const int8_t* side_tag, pm_mesh** out);
+void pm_mesh_destroy(pm_mesh* mesh);
+int pm_mesh_get_stats(const pm_mesh* mesh, pm_mesh_stats* stats);
+/* Host copies of the ordering and the CSR pattern (sizes n_cells, n_cells+1, nnz). */
+int pm_mesh_export(const pm_mesh* mesh, int32_t* perm, int32_t* row_ptr, int32_t* col);
+
+/*
+ * Assembles a corrector matrix on the GPU (eq. CS1_sys_coeff for PM_CP1X /
+ * PM_CP1Y, eq. CS2_sys_coeff for PM_CP2), with
+ *   M = I/dt + nu*eps*Kfrak            (Sec. 3.1: M0 = I + m dt, M = M0/dt)
+ *   Xi = eps * M^{-1}                  (eq. Cs2_4)
+ *   CP1 side weight  w = nu * T
+ *   CP2 side weight  w = T * n.((Xi_e + Xi_ep)/2).n   (boundary side: Xi_e)
+ *   a(e,ep) = -w;  a(e,e) = sum of side weights + Dirichlet weights
+ *                            + (CP1x: M11*A_e | CP1y: M22*A_e | CP2: 0).
+ * Dirichlet sides of the kind contribute T-weighted terms to the diagonal and
+ * w * g to b_lift; Neumann sides contribute nothing.
+ *   params       device, cell order (see pm_cell_params)
+ *   g_dirichlet  device [n_cells][3] Dirichlet values per side, cell order;
+ *                nullable (= 0)
+ *   val64        device [nnz] out, CSR values in the mesh's renumbered order
+ *   val32        device [nnz] out, nullable: val64 rounded to float32
+ *   dinv         device [n_cells] out, nullable: 1/diagonal, renumbered order
+ *   b_lift       device [n_cells] out, nullable: Dirichlet right-hand side, cell order
+ * Errors: PM_INVALID_ARG, PM_SINGULAR (CP2 with a component lacking a CP2
+ * Dirichlet side), PM_NONFINITE (non-finite or non-positive eps, non-finite
+ * parameters; checked on the device, reported after a stream sync).
+ */
+int assemble_corrector(pm_mesh* mesh, int32_t kind, const pm_cell_params* params, double nu,
+                       double dt, const double* g_dirichlet, double* val64, float* val32,
+                       double* dinv, double* b_lift, hipStream_t stream);
+
+/*
+ * Solves A x = b with Jacobi-preconditioned CG (Sec. 3.2.2 / 3.2.3 solve the
+ * corrector systems by PCG; the diagonal preconditioner replaces the paper's
+ * incomplete Cholesky).  The stopping test is the true residual
+ * ||b - A x||_2 <= tol ||b||_2, evaluated every replace_every iterations, where
+ * the recursive residual is also replaced by it and the accumulated increments
+ * are folded into x (group update).  x is carried as a double-double sum
+ * x_hi + x_lo between replacement points; the returned x is x_hi and the
+ * stopping test is the exact residual of that float64 vector.  PM_MIXED runs
+ * the Krylov recurrence on float32 copies with the same float64 solution,
+ * residual and test.
+ *   val64  device [nnz], CSR values on the mesh's pattern (renumbered order),
+ *          e.g. from assemble_corrector
+ *   b      device [n_cells], cell order
+ *   x      device [n_cells], cell order; initial guess in (unless
+ *          opts->x0_is_zero), solution out
+ *   opts   host, nullable (defaults); info host out, nullable
+ * Returns info->status (PM_OK, PM_MAXIT, PM_STAGNATED, PM_BREAKDOWN) or an
+ * error.
+ */
+int pcg_solve(pm_mesh* mesh, const double* val64, const double* b, double* x, const pm_opts* opts,
+              pm_info* info, hipStream_t stream);
+
+/*
+ * Groups several meshes (for instance permeability realisations on meshes of
+ * different sizes) for one batched solve.  The meshes must outlive the batch.
+ */
+int pm_batch_create(int32_t n_sys, pm_mesh* const* meshes, pm_batch** out);
+void pm_batch_destroy(pm_batch* batch);
+/* Offsets of system s in packed value and vector arrays: val_off[n_sys+1], vec_off[n_sys+1]. */
+int pm_batch_offsets(const pm_batch* batch, int64_t* val_off, int64_t* vec_off);
+
+/*
+ * Solves all systems of the batch in one persistent cooperative launch
+ * (captured in a HIP graph), each with its own scalars and convergence mask,
+ * with the same algorithm and stopping rule as pcg_solve.
+ *   val64  device, packed: system s occupies [val_off[s], val_off[s+1])
+ *   b, x   device, packed by vec_off, cell order within each system
+ *   infos  host [n_sys] out, nullable
+ * Returns PM_OK if every system converged, else the first non-OK status.
+ */
+int pcg_solve_batched(pm_batch* batch, const double* val64, const double* b, double* x,
+                      const pm_opts* opts, pm_info* infos, hipStream_t stream);
+
+/*
+ * Adjoint of x = A(theta)^{-1} (b + b_lift(theta)) for a loss L(x): solves
+ * A lambda = dL/dx with pcg_solve's algorithm (A is symmetric), then forms
+ *   dL/dtheta_c = lambda . (d b_lift/dtheta_c - (dA/dtheta_c) x)
+ * for theta = ln K and eps of every cell with one cell-wise gather kernel.
+ *   params, nu, dt, g_dirichlet  as given to assemble_corrector
+ *   val64      device [nnz], the assembled matrix
+ *   eta        device [n_cells], the forward solution, cell order
+ *   grad_eta   device [n_cells], dL/d eta, cell order
+ *   lambda     device [n_cells] out (= dL/db), cell order
+ *   grad_logk, grad_eps  device [n_cells] out, cell order
+ */
+int pcg_adjoint(pm_mesh* mesh, int32_t kind, const pm_cell_params* params, double nu, double dt,
+                const double* g_dirichlet, const double* val64, const double* eta,
+                const double* grad_eta, double* lambda, double* grad_logk, double* grad_eps,
+                const pm_opts* opts, pm_info* info, hipStream_t stream);
+
+/*
+ * Measurement hook: runs one of the solver's iteration kernels n_launch times
+ * on the state left by the last pcg_solve of this mesh (same precision and
+ * launch shape) between two HIP events on `stream`, and returns the mean
+ * duration in milliseconds and the bytes one launch must move.
+ *   which  0: matrix-vector product with fused dot products
+ *          1: vector update (x, z, p)
+ *          2: true-residual kernel (float64 CSR, compensated)
+ */
+int pm_time_kernel(pm_mesh* mesh, int32_t which, int32_t n_launch, hipStream_t stream,
+                   double* ms_per_launch, double* bytes_per_launch);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PMCORR_H */

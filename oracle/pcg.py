@@ -10,23 +10,29 @@ diagonal (Jacobi) one, which needs no sequential triangular sweeps.
 The paper states no tolerance.  The solver is specified as follows (the same
 specification the GPU library implements):
 
-  x = x0, x_acc = 0, r = b - A x (true residual), z = D^{-1} r, p = z,
-  rho = r.z
+  x = x_hi + x_lo (double-double, x_hi = x0, x_lo = 0), x_acc = 0,
+  r = b - A x (true residual), z = D^{-1} r, p = z, rho = r.z
   iteration k = 1, 2, ...:
     q = A p; alpha = rho / (p.q)   (breakdown if p.q <= 0 or not finite)
     x_acc += alpha p; r -= alpha q
     if k is a multiple of m:
-        x += x_acc; x_acc = 0                     (group update)
-        r = b - A x   (true residual, correctly rounded)
-        stop if ||r||_2 <= tol * ||b||_2
+        (x_hi, x_lo) += x_acc; x_acc = 0           (group update, double-double)
+        stop if ||b - A x_hi||_2 <= tol * ||b||_2  (the float64 vector returned)
+        r = b - A (x_hi + x_lo)                   (replacement)
+        stagnation: once ||b - A x_hi|| < 1000 max(tol ||b||, u || |A||x_hi| ||)
+        (u = 2^-53: the residual is near the rounding floor of float64), stop
+        with status STAGNATED if it has not halved over `stag_checks`
+        replacement points
     z = D^{-1} r; rho' = r.z; p = z + (rho'/rho) p; rho = rho'
 
-Two details are what make 1e-10 reachable on these matrices, whose
-transmissibilities span several decades: the increments are summed in a
-separate vector and folded into x only at replacement points (group update),
-and the true residual is evaluated exactly and then rounded, so the stopping
-test measures the iterate rather than the rounding of the check itself.  Here
-the residual is evaluated in x87 extended precision (64-bit significand),
+Three details make 1e-10 reachable on these matrices, whose
+transmissibilities span decades and whose right-hand sides may be tiny
+boundary fluxes: the increments are summed in a separate vector and folded
+into x only at replacement points (group update); x is carried as an
+unevaluated sum of two float64 vectors, so the iterate can get closer to the
+solution than one rounding; and residuals are evaluated exactly and then
+rounded, so the tests measure the iterate, not the rounding of the check.
+Here residuals are evaluated in x87 extended precision (64-bit significand),
 whose error is far below one float64 ulp of the result for these row lengths.
 """
 from __future__ import annotations
@@ -34,13 +40,23 @@ from __future__ import annotations
 import numpy as np
 import scipy.linalg as sla
 
-OK, MAXIT, BREAKDOWN = 0, 1, -6
+OK, MAXIT, STAGNATED, BREAKDOWN = 0, 1, 2, -6
 
 
-def true_residual(A, b, x) -> np.ndarray:
-    """b - A x evaluated in extended precision and rounded to float64."""
+def two_sum(a, b):
+    """Error-free sum: s + e == a + b exactly (Knuth)."""
+    s = a + b
+    bb = s - a
+    return s, (a - (s - bb)) + (b - bb)
+
+
+def true_residual(A, b, x, x_lo=None) -> np.ndarray:
+    """b - A (x + x_lo) evaluated in extended precision and rounded to float64."""
     ld = np.longdouble
-    prod = A.data.astype(ld) * np.asarray(x, np.float64).astype(ld)[A.indices]
+    xx = np.asarray(x, np.float64).astype(ld)
+    if x_lo is not None:
+        xx = xx + np.asarray(x_lo, np.float64).astype(ld)
+    prod = A.data.astype(ld) * xx[A.indices]
     if np.all(np.diff(A.indptr) > 0):
         s = np.add.reduceat(prod, A.indptr[:-1])
     else:
@@ -50,12 +66,14 @@ def true_residual(A, b, x) -> np.ndarray:
     return (np.asarray(b, np.float64).astype(ld) - s).astype(np.float64)
 
 
-def pcg(A, b, tol=1e-10, max_it=100000, replace_every=50, x0=None, record=False) -> tuple:
+def pcg(A, b, tol=1e-10, max_it=100000, replace_every=50, x0=None, record=False,
+        stag_checks=40) -> tuple:
     """Jacobi PCG with group-update residual replacement every `replace_every`
     iterations; returns (x, info) with info = iters, status, rel_res_true."""
     b = np.asarray(b, np.float64)
     n = b.shape[0]
     x = np.zeros(n) if x0 is None else np.array(x0, np.float64)
+    x_lo = np.zeros(n)
     bnorm = float(np.linalg.norm(b))
     info = {"iters": 0, "status": OK, "rel_res_true": 0.0, "history": []}
     if bnorm == 0.0:
@@ -70,6 +88,7 @@ def pcg(A, b, tol=1e-10, max_it=100000, replace_every=50, x0=None, record=False)
     z = dinv * r
     p = z.copy()
     rho = float(r @ z)
+    best, stall = res, 0
     k = 0
     while k < max_it:
         q = A @ p
@@ -82,20 +101,30 @@ def pcg(A, b, tol=1e-10, max_it=100000, replace_every=50, x0=None, record=False)
         r -= alpha * q
         k += 1
         if k % replace_every == 0:
-            x += xacc
+            s, e = two_sum(x, xacc)
+            x, x_lo = two_sum(s, e + x_lo)
             xacc[:] = 0.0
-            r = true_residual(A, b, x)
-            res = float(np.linalg.norm(r)) / bnorm
+            res = float(np.linalg.norm(true_residual(A, b, x))) / bnorm
             if record:
                 info["history"].append((k, res))
             if res <= tol:
                 info.update(iters=k, rel_res_true=res)
                 return x, info
+            if res < 0.5 * best:
+                best, stall = res, 0
+            else:
+                stall += 1
+            floor = 2.0 ** -53 * float(np.linalg.norm(abs(A) @ np.abs(x))) / bnorm
+            if best < 1e3 * max(tol, floor) and stall >= stag_checks:
+                info.update(iters=k, rel_res_true=res, status=STAGNATED)
+                return x, info
+            r = true_residual(A, b, x, x_lo)
         z = dinv * r
         rho_new = float(r @ z)
         p = z + (rho_new / rho) * p
         rho = rho_new
-    x += xacc
+    s, e = two_sum(x, xacc)
+    x, x_lo = two_sum(s, e + x_lo)
     info["iters"] = k
     info["rel_res_true"] = float(np.linalg.norm(true_residual(A, b, x))) / bnorm
     if info["status"] == OK:

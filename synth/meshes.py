@@ -25,19 +25,24 @@ from scipy.spatial import Delaunay
 G_NONE, G_LEFT, G_RIGHT, G_BOTTOM, G_TOP = 0, 1, 2, 3, 4
 
 
-def _triangulate(pts: np.ndarray) -> np.ndarray:
-    """Delaunay triangulation with CCW orientation; refuses coplanar points."""
+def _triangulate(pts: np.ndarray, with_neighbors: bool = False):
+    """Delaunay triangulation with CCW orientation; refuses coplanar points.
+    With with_neighbors, also returns nbr[e, j]: the triangle across the side
+    opposite node j (-1 on the hull)."""
     d = Delaunay(pts)
     if len(d.coplanar):
         raise RuntimeError(f"Qhull dropped {len(d.coplanar)} coplanar points")
     tri = d.simplices.astype(np.int64)
+    nbr = d.neighbors.astype(np.int64)
     p = pts[tri]
     s = (p[:, 1, 0] - p[:, 0, 0]) * (p[:, 2, 1] - p[:, 0, 1]) - (
         p[:, 1, 1] - p[:, 0, 1]
     ) * (p[:, 2, 0] - p[:, 0, 0])
     cw = s < 0
     tri[cw, 1], tri[cw, 2] = tri[cw, 2].copy(), tri[cw, 1].copy()
-    return np.ascontiguousarray(tri.astype(np.int32))
+    nbr[cw, 1], nbr[cw, 2] = nbr[cw, 2].copy(), nbr[cw, 1].copy()
+    tri = np.ascontiguousarray(tri.astype(np.int32))
+    return (tri, nbr) if with_neighbors else tri
 
 
 def _split_encroached(pts, x0, x1, y0, y1, margin=0.1, max_rounds=20):
@@ -45,7 +50,7 @@ def _split_encroached(pts, x0, x1, y0, y1, margin=0.1, max_rounds=20):
     angle wider than arccot(margin) (the node encroaches the side's diametral
     circle), add the side's midpoint as a boundary node and re-triangulate."""
     for _ in range(max_rounds):
-        tri = _triangulate(pts)
+        tri, nbr = _triangulate(pts, with_neighbors=True)
         P = pts[tri]
         add = []
         for j in range(3):
@@ -70,6 +75,74 @@ def _split_encroached(pts, x0, x1, y0, y1, margin=0.1, max_rounds=20):
         pts = np.concatenate([pts] + add)
         pts = np.unique(pts, axis=0)
     raise RuntimeError("boundary refinement did not terminate")
+
+
+def _side_quality(pts, tri, nbr):
+    """Cot sum of the two angles facing every interior side (Delaunay: > 0;
+    small values mean nearly cocircular quadrilaterals) and the four nodes of
+    the quadrilateral around that side."""
+    P = pts[tri]
+    cot = np.empty((tri.shape[0], 3))
+    for j in range(3):
+        a, b, c = P[:, j], P[:, (j + 1) % 3], P[:, (j + 2) % 3]
+        ux, uy = b[:, 0] - a[:, 0], b[:, 1] - a[:, 1]
+        vx, vy = c[:, 0] - a[:, 0], c[:, 1] - a[:, 1]
+        cot[:, j] = (ux * vx + uy * vy) / (ux * vy - uy * vx)
+    e, j = np.nonzero(nbr >= 0)
+    keep = e < nbr[e, j]  # each interior side once
+    e, j = e[keep], j[keep]
+    ep = nbr[e, j]
+    jp = np.argmax(nbr[ep] == e[:, None], axis=1)
+    cs = cot[e, j] + cot[ep, jp]
+    quad = np.stack([tri[e, j], tri[e, (j + 1) % 3], tri[e, (j + 2) % 3], tri[ep, jp]], 1)
+    return cs, quad
+
+
+def _untangle_cocircular(pts, movable, hl, x0, x1, y0, y1, seed, min_cot_sum=0.02, max_rounds=40):
+    """Mesh quality pass: each round triangulates once, splits encroached
+    boundary sides (as _split_encroached) and, for every interior side whose
+    facing angles are nearly supplementary (cot sum < min_cot_sum, i.e.
+    T = l/d > 2/min_cot_sum), deletes one movable node of its quadrilateral
+    (the one on the finest local spacing, then the lowest index), until
+    neither is left.  Deleting a node changes the local triangulation
+    decisively, so a few rounds suffice."""
+    for _ in range(max_rounds):
+        tri, nbr = _triangulate(pts, with_neighbors=True)
+        P = pts[tri]
+        add = []
+        for j in range(3):
+            a, b, c = P[:, (j + 1) % 3], P[:, (j + 2) % 3], P[:, j]
+            on = (((a[:, 0] == x0) & (b[:, 0] == x0)) | ((a[:, 0] == x1) & (b[:, 0] == x1))
+                  | ((a[:, 1] == y0) & (b[:, 1] == y0)) | ((a[:, 1] == y1) & (b[:, 1] == y1)))
+            ux, uy = a[:, 0] - c[:, 0], a[:, 1] - c[:, 1]
+            vx, vy = b[:, 0] - c[:, 0], b[:, 1] - c[:, 1]
+            bad = on & (ux * vx + uy * vy <= 0.1 * np.abs(ux * vy - uy * vx))
+            if np.any(bad):
+                mid = 0.5 * (a[bad] + b[bad])
+                vert = a[bad, 0] == b[bad, 0]
+                mid[vert, 0] = a[bad][vert, 0]
+                mid[~vert, 1] = a[bad][~vert, 1]
+                add.append(mid)
+        cs, quad = _side_quality(pts, tri, nbr)
+        drop = set()
+        for qd in quad[cs < min_cot_sum].tolist():
+            cand = [v for v in qd if movable[v]]
+            if cand and not drop.intersection(qd):
+                drop.add(min(cand, key=lambda v: (hl[v], v)))
+        if not add and not drop:
+            return pts, tri
+        keep = np.ones(len(pts), bool)
+        keep[list(drop)] = False
+        pts, movable, hl = pts[keep], movable[keep], hl[keep]
+        if add:
+            mid = np.concatenate(add)
+            pts = np.concatenate([pts, mid])
+            movable = np.concatenate([movable, np.zeros(len(mid), bool)])
+            hl = np.concatenate([hl, np.full(len(mid), hl.min())])
+            _, first = np.unique(pts, axis=0, return_index=True)
+            first = np.sort(first)
+            pts, movable, hl = pts[first], movable[first], hl[first]
+    raise RuntimeError("mesh quality pass did not converge")
 
 
 def _rect_groups(xy, tri, x0, x1, y0, y1) -> np.ndarray:
@@ -124,6 +197,7 @@ def graded_lattice(
     jitter: float = 0.15,
     level_of=None,
     max_level: int = 0,
+    quality: bool = True,
 ) -> dict:
     """Jittered triangular lattice on [0,L]x[0,H] with nested local refinement.
 
@@ -134,7 +208,11 @@ def graded_lattice(
     is stretched slightly so both x=0 and x=L fall on lattice columns; boundary
     rows at y=0 and y=H are lattice rows.  Boundary nodes are not jittered and
     neither are nodes within one local spacing of the boundary, so boundary
-    triangles stay acute at the node opposite the boundary side.
+    triangles stay acute at the node opposite the boundary side.  With
+    `quality`, nodes of nearly cocircular quadrilaterals (which the level
+    transitions create) are removed until every interior side has a cot sum
+    >= 0.02, i.e. a transmissibility l/d <= 100, as a quality mesh generator
+    would guarantee.
     """
     f = 2 ** max_level
     rows_f = n_rows * f
@@ -210,7 +288,11 @@ def graded_lattice(
     pts = pts.copy()
     pts[jit, 0] += rng.uniform(-jitter, jitter, m) * hl[jit]
     pts[jit, 1] += rng.uniform(-jitter, jitter, m) * hl[jit]
-    pts, tri = _split_encroached(pts, 0.0, L, 0.0, H)
+    if quality:
+        on_line = (pts[:, 0] == 0.0) | (pts[:, 0] == L) | (pts[:, 1] == 0.0) | (pts[:, 1] == H)
+        pts, tri = _untangle_cocircular(pts, ~on_line, hl, 0.0, L, 0.0, H, seed)
+    else:
+        pts, tri = _split_encroached(pts, 0.0, L, 0.0, H)
     return {"xy": pts, "tri": tri, "group": _rect_groups(pts, tri, 0.0, L, 0.0, H)}
 
 

@@ -1,0 +1,93 @@
+"""GPU batched solve: each system against the single-system solve and the oracle."""
+import functools
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import assemble as oasm  # noqa: E402
+from oracle import geometry, ordering  # noqa: E402
+from oracle import pcg as opcg  # noqa: E402
+from synth import workloads  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def B():
+    from paper_2309_03543_amd import binding
+
+    return binding
+
+
+@functools.lru_cache(maxsize=None)
+def batch_case(n_sys=5, lo=2000, hi=12000, seed=11):
+    ws = workloads.lognormal_batch(n_sys=n_sys, seed=seed, lo=lo, hi=hi)
+    dev = torch.device("cuda:0")
+    meshes, vals, bs, oracle = [], [], [], []
+    for w in ws:
+        m = w["mesh"]
+        mesh = B().Mesh(m["xy"], m["tri"], w["side_tag"])
+        prm = {k: torch.tensor(v, device=dev) for k, v in w["params"].items()}
+        vals.append(B().assemble_corrector(mesh, B().PM_CP2, prm, w["nu"], w["dt"])["val64"])
+        bs.append(torch.tensor(w["rhs"]["cp2"], device=dev))
+        meshes.append(mesh)
+        geo = geometry.build(m["xy"], m["tri"], w["side_tag"])
+        perm = ordering.rcm(geo["nbr"])
+        A = oasm.assemble(geo, perm, oasm.CP2, w["params"], w["nu"], w["dt"])["A"]
+        oracle.append((perm, A, w["rhs"]["cp2"][perm]))
+    batch = B().Batch(meshes)
+    return {"ws": ws, "meshes": meshes, "vals": vals, "bs": bs, "batch": batch, "oracle": oracle}
+
+
+def packed(c):
+    return torch.cat(c["vals"]), torch.cat(c["bs"])
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batched_matches_single_and_oracle(precision):
+    c = batch_case()
+    batch = c["batch"]
+    assert batch.vec_off[-1] == sum(m.n for m in c["meshes"])
+    val, b = packed(c)
+    x, infos = B().pcg_solve_batched(batch, val, b, precision=precision)
+    torch.cuda.synchronize()
+    for s, (mesh, info) in enumerate(zip(c["meshes"], infos)):
+        xs = x[batch.vec_off[s]: batch.vec_off[s + 1]]
+        x1, i1 = B().pcg_solve(mesh, c["vals"][s], c["bs"][s], precision=precision)
+        assert info["status"] == 0 and i1["status"] == 0
+        assert abs(info["iters"] - i1["iters"]) <= 50
+        perm, A, bo = c["oracle"][s]
+        xg = xs.cpu().numpy()[perm]
+        assert opcg.rel_residual(A, bo, xg) <= 1e-10
+        assert abs(info["rel_res_true"] - opcg.rel_residual(A, bo, xg)) <= 1e-2 * info["rel_res_true"] + 1e-16
+        ref = x1.cpu().numpy()[perm]
+        assert np.linalg.norm(xg - ref) <= 1e-9 * np.linalg.norm(ref)
+        if precision == 0:
+            xo, io = opcg.pcg(A, bo, tol=1e-10)
+            assert np.linalg.norm(xg - xo) <= 1e-9 * np.linalg.norm(xo)
+
+
+def test_batched_replays_are_identical_and_masks_a_bad_system():
+    c = batch_case()
+    batch = c["batch"]
+    val, b = packed(c)
+    x1, i1 = B().pcg_solve_batched(batch, val, b)
+    x2, i2 = B().pcg_solve_batched(batch, val, b)
+    assert torch.equal(x1, x2) and [i["iters"] for i in i1] == [i["iters"] for i in i2]
+    bad = b.clone()
+    bad[int(batch.vec_off[2]) + 3] = float("nan")
+    x3, i3 = B().pcg_solve_batched(batch, val, bad)
+    for s in range(len(c["meshes"])):
+        sl = slice(int(batch.vec_off[s]), int(batch.vec_off[s + 1]))
+        if s == 2:
+            assert i3[s]["status"] == B().PM_NONFINITE
+        else:
+            assert i3[s]["status"] == 0 and torch.equal(x3[sl], x1[sl])
+
+
+def test_batched_iteration_limit():
+    c = batch_case()
+    val, b = packed(c)
+    x, infos = B().pcg_solve_batched(c["batch"], val, b, max_it=20)
+    assert all(i["status"] == B().PM_MAXIT and i["iters"] == 20 for i in infos)

@@ -1,0 +1,196 @@
+"""GPU parity: the HIP library against the CPU oracle on the same seeded inputs.
+
+Tolerances
+  * CSR structure and ordering: bit-exact (integer work).
+  * Assembled values: |gpu - oracle| <= 1e-13 |oracle| per entry (the two
+    differ only in the rounding of exp and the order of a few products).
+  * FP64 and mixed solves: true relative residual <= 1e-10 (evaluated by the
+    oracle on the GPU solution) and relative error <= 1e-9 against the oracle's
+    float64 solution; iteration counts within one replacement period.
+"""
+import functools
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import assemble as oasm  # noqa: E402
+from oracle import geometry, ordering  # noqa: E402
+from oracle import pcg as opcg  # noqa: E402
+from synth import meshes, workloads  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+KIND = {"cp1x": oasm.CP1X, "cp1y": oasm.CP1Y, "cp2": oasm.CP2}
+
+
+def B():
+    from paper_2309_03543_amd import binding
+
+    return binding
+
+
+@functools.lru_cache(maxsize=None)
+def case(name):
+    if name == "c1":
+        w = workloads.square_inclusion()
+    elif name == "chan":
+        w = workloads.channel(30, 2)
+    elif name == "aniso":
+        w = workloads.channel(30, 3, aniso=True)
+    elif name == "tiny":
+        w = workloads.square_inclusion(npts=5, seed=2)
+    else:
+        raise KeyError(name)
+    m = w["mesh"]
+    geo = geometry.build(m["xy"], m["tri"], w["side_tag"])
+    perm = ordering.rcm(geo["nbr"])
+    mesh = B().Mesh(m["xy"], m["tri"], w["side_tag"])
+    dev = torch.device("cuda:0")
+    prm = {k: torch.tensor(v, device=dev) for k, v in w["params"].items()}
+    return {"w": w, "geo": geo, "perm": perm, "mesh": mesh, "prm": prm, "dev": dev}
+
+
+def oracle_matrix(c, kind, g=None):
+    w = c["w"]
+    return oasm.assemble(c["geo"], c["perm"], KIND[kind], w["params"], w["nu"], w["dt"], g)
+
+
+def to_perm(c, v):
+    return np.asarray(v)[c["perm"]]
+
+
+@pytest.mark.parametrize("name", ["c1", "chan", "aniso", "tiny"])
+def test_structure_export_matches_oracle(name):
+    c = case(name)
+    perm, rp, col = c["mesh"].export()
+    rp2, col2 = ordering.csr_pattern(c["geo"]["nbr"], c["perm"])
+    assert np.array_equal(perm, c["perm"]) and np.array_equal(rp, rp2) and np.array_equal(col, col2)
+
+
+@pytest.mark.parametrize("name", ["c1", "chan", "aniso"])
+@pytest.mark.parametrize("kind", ["cp1x", "cp1y", "cp2"])
+def test_assembly_matches_oracle(name, kind):
+    c = case(name)
+    w = c["w"]
+    n = c["geo"]["n"]
+    g = np.random.default_rng(5).standard_normal((n, 3))
+    o = oracle_matrix(c, kind, g)
+    gd = torch.tensor(g, device=c["dev"])
+    out = B().assemble_corrector(c["mesh"], KIND[kind], c["prm"], w["nu"], w["dt"], g_dirichlet=gd,
+                                 val32=True, dinv=True, b_lift=True)
+    v = out["val64"].cpu().numpy()
+    ref = o["A"].data
+    assert np.all(np.abs(v - ref) <= 1e-13 * np.abs(ref))
+    # one weight per side: the GPU matrix is bitwise symmetric
+    import scipy.sparse as sp
+
+    A = sp.csr_matrix((v, o["A"].indices, o["A"].indptr), shape=o["A"].shape)
+    assert (A != A.T).nnz == 0
+    assert np.array_equal(out["val32"].cpu().numpy(), v.astype(np.float32))
+    np.testing.assert_array_equal(out["dinv"].cpu().numpy(), 1.0 / A.diagonal())
+    bl = out["b_lift"].cpu().numpy()
+    assert np.all(np.abs(bl - o["b_lift"]) <= 1e-13 * np.abs(o["b_lift"]) + 1e-300)
+
+
+def solve_both(name, kind, precision, rhs=None, **kw):
+    c = case(name)
+    w = c["w"]
+    A = oracle_matrix(c, kind)["A"]
+    b = w["rhs"][rhs or ("cp1x" if kind.startswith("cp1") else "cp2")]
+    val = B().assemble_corrector(c["mesh"], KIND[kind], c["prm"], w["nu"], w["dt"])["val64"]
+    bt = torch.tensor(b, device=c["dev"])
+    x, info = B().pcg_solve(c["mesh"], val, bt, precision=precision, **kw)
+    torch.cuda.synchronize()
+    xo, io = opcg.pcg(A, to_perm(c, b), tol=kw.get("tol", 1e-10), max_it=kw.get("max_it", 100000),
+                      replace_every=kw.get("replace_every", 50), stag_checks=kw.get("stag_checks", 40))
+    return c, A, to_perm(c, b), to_perm(c, x.cpu().numpy()), info, xo, io
+
+
+@pytest.mark.parametrize("name,kind", [("c1", "cp2"), ("chan", "cp2"), ("chan", "cp1x"),
+                                       ("aniso", "cp2"), ("aniso", "cp1y"), ("tiny", "cp2")])
+def test_fp64_solve_matches_oracle(name, kind):
+    c, A, b, xg, info, xo, io = solve_both(name, kind, 0)
+    assert info["status"] == 0 and io["status"] == 0
+    res = opcg.rel_residual(A, b, xg)
+    assert res <= 1e-10
+    assert abs(info["rel_res_true"] - res) <= 1e-2 * res + 1e-16
+    assert np.linalg.norm(xg - xo) <= 1e-9 * np.linalg.norm(xo)
+    assert abs(info["iters"] - io["iters"]) <= max(50, 0.02 * io["iters"])
+
+
+@pytest.mark.parametrize("name,kind", [("c1", "cp2"), ("chan", "cp2"), ("aniso", "cp2"), ("chan", "cp1x")])
+def test_mixed_solve_reaches_fp64_accuracy(name, kind):
+    c, A, b, xg, info, xo, io = solve_both(name, kind, 1)
+    assert info["status"] == 0
+    res = opcg.rel_residual(A, b, xg)
+    assert res <= 1e-10
+    err = np.linalg.norm(xg - xo) / np.linalg.norm(xo)
+    print(f"mixed {name} {kind}: iters {info['iters']} vs fp64 oracle {io['iters']}, err {err:.2e}")
+    assert err <= 1e-9
+
+
+def test_iteration_limit_and_partial_iterate():
+    c, A, b, xg, info, xo, io = solve_both("c1", "cp2", 0, max_it=7)
+    assert info["status"] == B().PM_MAXIT and info["iters"] == 7
+    assert io["status"] == opcg.MAXIT and io["iters"] == 7
+    assert np.linalg.norm(xg - xo) <= 1e-10 * np.linalg.norm(xo)
+
+
+def test_warm_start_and_zero_rhs():
+    c = case("c1")
+    w = c["w"]
+    val = B().assemble_corrector(c["mesh"], B().PM_CP2, c["prm"], w["nu"], w["dt"])["val64"]
+    b = torch.tensor(w["rhs"]["cp2"], device=c["dev"])
+    x, info = B().pcg_solve(c["mesh"], val, b)
+    x2, info2 = B().pcg_solve(c["mesh"], val, b, x=x.clone(), x0_is_zero=False)
+    assert info2["iters"] == 0 and info2["status"] == 0
+    z = torch.zeros_like(b)
+    x3, info3 = B().pcg_solve(c["mesh"], val, z, x=torch.ones_like(b), x0_is_zero=False)
+    assert info3["status"] == 0 and info3["iters"] == 0 and not torch.any(x3)
+
+
+def test_solves_are_deterministic_and_launch_shape_independent():
+    c = case("chan")
+    w = c["w"]
+    val = B().assemble_corrector(c["mesh"], B().PM_CP2, c["prm"], w["nu"], w["dt"])["val64"]
+    b = torch.tensor(w["rhs"]["cp2"], device=c["dev"])
+    x1, i1 = B().pcg_solve(c["mesh"], val, b)
+    x2, i2 = B().pcg_solve(c["mesh"], val, b)
+    assert torch.equal(x1, x2) and i1["iters"] == i2["iters"]
+    for grid in (1, 3, 17):
+        x3, i3 = B().pcg_solve(c["mesh"], val, b, grid=grid)
+        assert i3["status"] == 0
+        assert torch.linalg.norm(x3 - x1) <= 1e-9 * torch.linalg.norm(x1)
+
+
+def test_error_statuses():
+    Bm = B()
+    c = case("tiny")
+    w = c["w"]
+    bad = dict(c["prm"])
+    bad["eps"] = c["prm"]["eps"].clone()
+    bad["eps"][0] = float("nan")
+    with pytest.raises(Bm.PMError) as e:
+        Bm.assemble_corrector(c["mesh"], Bm.PM_CP2, bad, w["nu"], w["dt"])
+    assert e.value.status == Bm.PM_NONFINITE
+    val = Bm.assemble_corrector(c["mesh"], Bm.PM_CP2, c["prm"], w["nu"], w["dt"])["val64"]
+    b = torch.tensor(w["rhs"]["cp2"], device=c["dev"])
+    b[1] = float("inf")
+    with pytest.raises(Bm.PMError) as e:
+        Bm.pcg_solve(c["mesh"], val, b)
+    assert e.value.status == Bm.PM_NONFINITE
+    # CP2 on a mesh without a CP2 Dirichlet side is singular
+    m = w["mesh"]
+    tag = np.where(w["side_tag"] & 2, 1, w["side_tag"]).astype(np.int8)
+    mesh2 = Bm.Mesh(m["xy"], m["tri"], tag)
+    with pytest.raises(Bm.PMError) as e:
+        Bm.assemble_corrector(mesh2, Bm.PM_CP2, c["prm"], w["nu"], w["dt"])
+    assert e.value.status == Bm.PM_SINGULAR
+
+
+def test_unreachable_tolerance_stagnates_like_the_oracle():
+    c, A, b, xg, info, xo, io = solve_both("tiny", "cp2", 0, tol=1e-19, stag_checks=10)
+    assert info["status"] == B().PM_STAGNATED and io["status"] == opcg.STAGNATED
+    assert opcg.rel_residual(A, b, xg) < 1e-12

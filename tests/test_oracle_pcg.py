@@ -61,3 +61,22 @@ def test_statuses():
     indef = sp.csr_matrix(np.diag([1.0, -1.0, 2.0]))
     x, info = pcg.pcg(indef, np.array([1.0, 1.0, 1.0]))
     assert info["status"] == pcg.BREAKDOWN
+
+
+def test_two_sum_is_error_free():
+    from fractions import Fraction
+
+    rng = np.random.default_rng(0)
+    a = rng.standard_normal(200) * 10.0 ** rng.integers(-8, 8, 200)
+    b = rng.standard_normal(200) * 10.0 ** rng.integers(-8, 8, 200)
+    s, e = pcg.two_sum(a, b)
+    for ai, bi, si, ei in zip(a, b, s, e):
+        assert Fraction(si) + Fraction(ei) == Fraction(ai) + Fraction(bi)
+        assert abs(ei) <= abs(np.spacing(si))
+
+
+def test_unreachable_tolerance_reports_stagnation():
+    A, b = system(npts=12)
+    x, info = pcg.pcg(A, b, tol=1e-19, max_it=50000, stag_checks=10)
+    assert info["status"] == pcg.STAGNATED and info["iters"] < 50000
+    assert info["rel_res_true"] < 1e-12
