@@ -1,14 +1,24 @@
 """Benchmark of the corrector hot path on one MI355X.
 
-A step is one pass of the hot path over the workload: assembly of the CP1x
-and CP2 matrices from the per-cell fields, then a PCG solve of each to a true
-relative residual of 1e-10.  The reported value is corrector solves per
-second (whole job), float64; the same step in mixed precision, the roofline of
-the dominant iteration kernel and the CPU oracle on a bounded sample are
-reported beside it.  Inputs are seeded and synthetic (synth/), resident in
-HBM before timing starts.
+A step is one pass of the hot path over the workload: GPU assembly of the
+corrector matrices from the per-cell fields, then a Jacobi-PCG solve of each
+to a true relative residual of 1e-10.  `value` is corrector solves per second
+in float64 (whole job, one GPU); the same step in mixed precision, the
+roofline of the dominant iteration kernel and the CPU oracle on a bounded
+sample are reported beside it.  Inputs are seeded and synthetic (synth/) and
+resident in HBM before timing starts.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload channel|square|channel_aniso]
+Workloads (--workload)
+  channel        4x1 channel with a porous block, ~1.0M triangles refined 4x
+                 near the block, isotropic K; CP1x and CP2 per step (default)
+  channel_aniso  the same recipe at ~4.0M triangles with anisotropic K (ratio
+                 100 rotated 30 deg); CP2 per step
+  square         unit square 64x64 jittered grid (~8k triangles); CP2
+  batch          64 unit squares of 50k-500k triangles with log-normal K;
+                 one batched CP2 solve per step
+  adjoint        channel forward CP2 solve + adjoint solve + gradient kernel
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
 from __future__ import annotations
 
@@ -27,22 +37,11 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+METRIC = "corrector PCG solves/s + SpMV HBM GB/s, mixed vs FP64 at 1e-10 residual"
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
-
-
-def build_workload(name):
-    from synth import workloads
-
-    if name == "channel":
-        return workloads.channel(276, 2), "channel_1M"
-    if name == "channel_aniso":
-        return workloads.channel(552, 3, aniso=True), "channel_aniso_4M"
-    if name == "square":
-        return workloads.square_inclusion(), "square_inclusion_8k"
-    raise SystemExit(f"unknown workload {name}")
 
 
 def main():
@@ -56,90 +55,134 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: the corrector library is a single-GPU build "
-              "(the multi-GPU sharding is a design note only); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: this corrector library is a single-GPU build and "
+              "its multi-GPU sharding is a design note only; run it with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
 
     from paper_2309_03543_amd import binding as B
+    from synth import workloads
 
     dev = torch.device("cuda:0")
-    t0 = time.time()
-    w, wname = build_workload(args.workload)
-    m = w["mesh"]
-    log(f"workload {wname}: {m['tri'].shape[0]} cells, generated in {time.time() - t0:.1f}s")
-    t0 = time.time()
-    mesh = B.Mesh(m["xy"], m["tri"], w["side_tag"])
-    st = mesh.stats
-    log(f"mesh: n={st['n_cells']} nnz={st['nnz']} bw={st['bandwidth']} idx={st['index_bits']}b "
-        f"maxT={st['max_T']:.3g} ({time.time() - t0:.1f}s)")
-    prm = {k: torch.tensor(v, device=dev) for k, v in w["params"].items()}
-    rhs = {k: torch.tensor(w["rhs"][k], device=dev) for k in ("cp1x", "cp2")}
-    nu, dt = w["nu"], w["dt"]
     stream = torch.cuda.current_stream()
+    wl = args.workload
+    t0 = time.time()
+    if wl == "batch":
+        ws = workloads.lognormal_batch()
+        wname = "lognormal_batch_64x50k-500k"
+    elif wl == "channel_aniso":
+        ws = [workloads.channel(552, 3, aniso=True)]
+        wname = "channel_aniso_4M"
+    elif wl == "square":
+        ws = [workloads.square_inclusion()]
+        wname = "square_inclusion_8k"
+    elif wl in ("channel", "adjoint"):
+        ws = [workloads.channel(276, 2)]
+        wname = "channel_1M" if wl == "channel" else "channel_1M_adjoint"
+    else:
+        raise SystemExit(f"unknown workload {wl}")
+    log(f"workload {wname}: {sum(w['mesh']['tri'].shape[0] for w in ws)} cells, "
+        f"generated in {time.time() - t0:.1f}s")
+    t0 = time.time()
+    meshes = [B.Mesh(w["mesh"]["xy"], w["mesh"]["tri"], w["side_tag"]) for w in ws]
+    prms = [{k: torch.tensor(v, device=dev) for k, v in w["params"].items()} for w in ws]
+    n_cells = sum(m.n for m in meshes)
+    nnz = sum(m.nnz for m in meshes)
+    log(f"meshes ready in {time.time() - t0:.1f}s: n={n_cells} nnz={nnz} "
+        f"maxT={max(m.stats['max_T'] for m in meshes):.3g} idx={meshes[0].stats['index_bits']}b")
+
+    kinds = {"channel": [("cp1x", B.PM_CP1X), ("cp2", B.PM_CP2)]}.get(wl, [("cp2", B.PM_CP2)])
+    rhs = [{k: torch.tensor(w["rhs"][k], device=dev) for k, _ in kinds} for w in ws]
+    batch = B.Batch(meshes) if wl == "batch" else None
+    w0, mesh0, prm0 = ws[0], meshes[0], prms[0]
+    probes = torch.tensor(np.random.default_rng(5).choice(n_cells, 256, replace=False), device=dev)
 
     def step(precision):
         infos = []
-        for kind, key in ((B.PM_CP1X, "cp1x"), (B.PM_CP2, "cp2")):
-            val = B.assemble_corrector(mesh, kind, prm, nu, dt)["val64"]
-            x, info = B.pcg_solve(mesh, val, rhs[key], precision=precision, tol=1e-10)
+        if wl == "batch":
+            vals = [B.assemble_corrector(m, B.PM_CP2, p, w["nu"], w["dt"])["val64"]
+                    for m, p, w in zip(meshes, prms, ws)]
+            b = torch.cat([r["cp2"] for r in rhs])
+            x, inf = B.pcg_solve_batched(batch, torch.cat(vals), b, precision=precision)
+            bad = [i for i in inf if i["status"] != 0]
+            if bad:
+                raise RuntimeError(f"batched solve failed: {bad[0]}")
+            return inf
+        for key, kind in kinds:
+            val = B.assemble_corrector(mesh0, kind, prm0, w0["nu"], w0["dt"])["val64"]
+            x, info = B.pcg_solve(mesh0, val, rhs[0][key], precision=precision)
             if info["status"] != 0:
                 raise RuntimeError(f"solve {key} failed: {info}")
             infos.append(info)
+            if wl == "adjoint":
+                g = torch.zeros_like(x)
+                g[probes] = 2.0 * x[probes]
+                lam, gs, ge, ia = B.pcg_adjoint(mesh0, kind, prm0, w0["nu"], w0["dt"], val, x, g,
+                                                precision=precision)
+                if ia["status"] != 0:
+                    raise RuntimeError(f"adjoint solve failed: {ia}")
+                infos.append(ia)
         return infos
 
     def timed(precision):
         for _ in range(args.warmup):
             step(precision)
         torch.cuda.synchronize()
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ev0.record(stream)
         t = time.perf_counter()
         infos = []
         for k in range(args.steps):
             infos.append(step(precision))
-            log(f"  step {k + 1}/{args.steps} precision={precision} iters="
-                f"{[i['iters'] for i in infos[-1]]} res={['%.2e' % i['rel_res_true'] for i in infos[-1]]}")
-        ev1.record(stream)
+            its = [i["iters"] for i in infos[-1]]
+            log(f"  step {k + 1}/{args.steps} precision={precision} iters={its if len(its) < 8 else (min(its), max(its))} "
+                f"max_res={max(i['rel_res_true'] for i in infos[-1]):.2e}")
         torch.cuda.synchronize()
-        wall = time.perf_counter() - t
-        gpu_ms = ev0.elapsed_time(ev1)
-        return wall, gpu_ms, infos
+        return time.perf_counter() - t, infos
 
     log("timing float64 steps")
-    wall64, gms64, inf64 = timed(0)
-    solves = 2 * args.steps
-    value = solves / wall64
-    # roofline of the dominant kernel, measured on the state of the last CP2 solve
-    ms_spmv, by_spmv = B.pm_time_kernel(mesh, 0, 200)
-    ms_upd, by_upd = B.pm_time_kernel(mesh, 1, 200)
-    dom = ("k_spmv", ms_spmv, by_spmv) if ms_spmv >= ms_upd else ("k_update", ms_upd, by_upd)
-    achieved = dom[2] / (dom[1] * 1e-3) / 1e9
-    it64 = [i["iters"] for i in inf64[-1]]
+    wall64, inf64 = timed(0)
+    solves_per_step = len(inf64[-1])
+    value = solves_per_step * args.steps / wall64
+    # per-kernel timing on the state of the last solve of the step
+    tmesh = mesh0 if batch is None else None
+    kern = {}
+    if tmesh is not None:
+        for name, which, reps in (("k_spmv", 0, 200), ("k_update", 1, 200), ("k_resid", 2, 20)):
+            ms, by = B.pm_time_kernel(tmesh, which, reps)
+            kern[name] = {"ms": ms, "bytes": by, "GBs": by / ms / 1e6}
+        it_last = inf64[-1][-1]["iters"]
+        dom = max(("k_spmv", "k_update"), key=lambda k: kern[k]["ms"])
+        achieved = kern[dom]["GBs"]
+        roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "ms_per_launch": kern[dom]["ms"], "bytes_per_launch": kern[dom]["bytes"],
+                "launches_per_solve": it_last}
+    else:
+        roof = None
 
     mixed = None
     if not args.no_mixed:
         log("timing mixed steps")
-        wallm, gmsm, infm = timed(1)
+        wallm, infm = timed(1)
         mixed = {
-            "solves_per_s": solves / wallm,
-            "speedup_vs_fp64": (solves / wallm) / value,
-            "iters": [i["iters"] for i in infm[-1]],
-            "rel_res_true": [i["rel_res_true"] for i in infm[-1]],
+            "solves_per_s": solves_per_step * args.steps / wallm,
+            "speedup_vs_fp64": (solves_per_step * args.steps / wallm) / value,
+            "iters": [i["iters"] for i in infm[-1]][:8],
+            "max_rel_res_true": max(i["rel_res_true"] for i in infm[-1]),
         }
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and wl != "batch":
         log("timing the CPU oracle on a bounded sample")
         from oracle import assemble as oasm
-        from oracle import geometry, ordering
+        from oracle import geometry
         from oracle import pcg as opcg
 
-        perm, _, _ = mesh.export()
-        geo = geometry.build(m["xy"], m["tri"], w["side_tag"])
-        A = oasm.assemble(geo, perm, oasm.CP2, w["params"], nu, dt)["A"]
-        b = w["rhs"]["cp2"][perm]
+        perm, _, _ = mesh0.export()
+        m = w0["mesh"]
+        geo = geometry.build(m["xy"], m["tri"], w0["side_tag"])
+        A = oasm.assemble(geo, perm, oasm.CP2, w0["params"], w0["nu"], w0["dt"])["A"]
+        b = w0["rhs"]["cp2"][perm]
         k = 50
         t = time.perf_counter()
         opcg.pcg(A, b, tol=1e-10, max_it=k)
@@ -148,19 +191,20 @@ def main():
         t = time.perf_counter()
         opcg.pcg(A, b, tol=1e-10, max_it=k)
         per_it = (time.perf_counter() - t) / k
-        sec_per_solve = per_it * (it64[1] + it64[0])
+        its = [i["iters"] for i in inf64[-1]]
+        sec_per_step = per_it * sum(its)
         cpu = {
-            "value": 2.0 / sec_per_solve,
+            "value": solves_per_step / sec_per_step,
             "unit": "solves/s",
             "cores": 1,
             "kind": "oracle",
-            "sample": f"oracle Jacobi-PCG on the CP2 system of this workload, {k} iterations "
-                      f"({per_it * 1e3:.1f} ms/iteration, single-threaded NumPy/SciPy), scaled to the "
-                      f"GPU step's {it64[0]}+{it64[1]} iterations",
+            "sample": f"oracle Jacobi-PCG (NumPy/SciPy, single thread) on this workload's CP2 "
+                      f"system: {k} iterations at {per_it * 1e3:.2f} ms each, scaled to the "
+                      f"{sum(its)} iterations of one GPU step ({'+'.join(map(str, its))})",
         }
 
     out = {
-        "metric": "corrector PCG solves/s (FP64, 1e-10 true residual)",
+        "metric": METRIC,
         "value": value,
         "unit": "solves/s",
         "n_gpus": 1,
@@ -172,13 +216,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": wname, "n_cells": st["n_cells"], "nnz": st["nnz"],
-                   "systems_per_step": ["CP1x", "CP2"], "iters": it64, "tol": 1e-10},
-        "roofline": {"bound": "hbm", "kernel": dom[0], "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "ms_per_launch": dom[1], "bytes_per_launch": dom[2]},
-        "kernels": {"k_spmv": {"ms": ms_spmv, "GBs": by_spmv / ms_spmv / 1e6},
-                    "k_update": {"ms": ms_upd, "GBs": by_upd / ms_upd / 1e6}},
+        "config": {"workload": wname, "n_cells": n_cells, "nnz": nnz, "systems": len(ws),
+                   "solves_per_step": solves_per_step, "tol": 1e-10,
+                   "iters": [i["iters"] for i in inf64[-1]][:8]},
+        "roofline": roof,
+        "kernels": kern,
         "mixed": mixed,
         "cpu_baseline": cpu,
     }

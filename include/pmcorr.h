@@ -105,8 +105,9 @@ typedef struct {
   int32_t replace_every; /* true-residual replacement period m (default 50); the
                             stopping test runs at these points */
   int32_t x0_is_zero;    /* 1: ignore x on entry and start from 0 */
-  int32_t block;         /* threads per block for the iteration kernels; 0 = tuned */
-  int32_t grid;          /* blocks for the iteration kernels; 0 = tuned */
+  int32_t block;         /* threads per block of the iteration kernels (0 = 256) */
+  int32_t tile_rows;     /* rows per work tile (one block each; >= 256); 0 = chosen
+                            by the built-in tuner and cached per problem shape */
   int32_t stag_checks;   /* replacement points without the residual halving, once
                             below 1000*max(tol*||b||, u*|| |A||x| ||), before
                             PM_STAGNATED (default 40) */
@@ -222,9 +223,12 @@ void pm_batch_destroy(pm_batch* batch);
 int pm_batch_offsets(const pm_batch* batch, int64_t* val_off, int64_t* vec_off);
 
 /*
- * Solves all systems of the batch in one persistent cooperative launch
- * (captured in a HIP graph), each with its own scalars and convergence mask,
- * with the same algorithm and stopping rule as pcg_solve.
+ * Solves all systems of the batch together with the algorithm and stopping
+ * rule of pcg_solve: every launch of an iteration kernel covers the row tiles
+ * of all systems still running, each system with its own scalars, test and
+ * stop flag (a converged system is masked out of later launches); one replay
+ * of the captured HIP graph advances the whole batch by replace_every
+ * iterations.
  *   val64  device, packed: system s occupies [val_off[s], val_off[s+1])
  *   b, x   device, packed by vec_off, cell order within each system
  *   infos  host [n_sys] out, nullable

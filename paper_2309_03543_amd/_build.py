@@ -31,6 +31,7 @@ def build(verbose: bool = False) -> str:
     jobs = [
         ("mesh_host.cpp", COMMON),
         ("pmcorr.hip", COMMON + DEVICE),
+        ("solver.hip", COMMON + DEVICE),
         ("batched.hip", COMMON + DEVICE),
     ]
     procs = []

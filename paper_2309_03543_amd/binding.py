@@ -41,7 +41,7 @@ class pm_opts(C.Structure):
     _fields_ = [
         ("tol", C.c_double), ("max_it", C.c_int32), ("precision", C.c_int32),
         ("replace_every", C.c_int32), ("x0_is_zero", C.c_int32), ("block", C.c_int32),
-        ("grid", C.c_int32), ("stag_checks", C.c_int32),
+        ("tile_rows", C.c_int32), ("stag_checks", C.c_int32),
     ]
 
 
@@ -221,11 +221,11 @@ def assemble_corrector(mesh: Mesh, kind: int, params: dict, nu: float, dt: float
 
 
 def make_opts(tol=1e-10, max_it=200000, precision=PM_FP64, replace_every=50, x0_is_zero=True,
-              block=0, grid=0, stag_checks=40) -> pm_opts:
+              block=0, tile_rows=0, stag_checks=40) -> pm_opts:
     o = pm_opts()
     lib().pm_opts_default(C.addressof(o))
     o.tol, o.max_it, o.precision, o.replace_every = tol, max_it, precision, replace_every
-    o.x0_is_zero, o.block, o.grid = int(bool(x0_is_zero)), block, grid
+    o.x0_is_zero, o.block, o.tile_rows = int(bool(x0_is_zero)), block, tile_rows
     o.stag_checks = stag_checks
     return o
 

@@ -8,21 +8,7 @@
 
 namespace pm {
 
-constexpr int kMaxBlocks = 4096;  // upper bound on blocks of a reducing kernel
 constexpr int kNumXcd = 8;        // MI355X: 8 accelerator complex dies, 32 CUs each
-
-// Solver state shared by the kernels of one solve (device memory).
-struct State {
-  double alpha, beta, rho;   // current CG scalars
-  double bnorm2, tol2;       // ||b||^2 and tol^2 * ||b||^2
-  double res2;               // last true residual ||b - A x_hi||^2
-  double best_res2;          // smallest res2 seen (stagnation test)
-  int32_t iter, max_it;      // completed iterations, limit
-  int32_t done, status;      // stop flag (checked by every kernel), PM_* status
-  int32_t err;               // input check failures (PM_* code, 0 = none)
-  int32_t stall, stag_checks;  // replacement points since res2 last halved, limit
-  int32_t iter_pending;      // iteration the current product belongs to
-};
 
 // Blocks are dispatched round-robin over the XCDs; renumber them so each XCD
 // works on one contiguous range of rows and the neighbour gathers of adjacent

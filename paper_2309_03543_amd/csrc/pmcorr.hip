@@ -29,8 +29,7 @@
 
 #include "kernels.h"
 #include "pm_internal.h"
-
-using pm::State;
+#include "solver.h"
 
 namespace pm {
 
@@ -63,7 +62,7 @@ __global__ void k_cell_tensors(int n, const int* __restrict__ perm, const double
                                const double* __restrict__ g22, double nu, double dt,
                                double* __restrict__ X11, double* __restrict__ X12,
                                double* __restrict__ X22, double* __restrict__ M11,
-                               double* __restrict__ M22, State* st) {
+                               double* __restrict__ M22, int32_t* err) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int o = perm[i];
@@ -73,11 +72,11 @@ __global__ void k_cell_tensors(int n, const int* __restrict__ perm, const double
   const bool finite_in = isfinite(e) && isfinite(s) && isfinite(ch) && isfinite(a11) &&
                          isfinite(a12) && isfinite(a22);
   if (!finite_in) {
-    atomicExch(&st->err, PM_NONFINITE);
+    atomicExch(err, PM_NONFINITE);
     return;
   }
-  if (!(e > 0.0) || ch < 0.0 || !(a11 > 0.0) || !(a11 * a22 - a12 * a12 > 0.0)) {
-    atomicExch(&st->err, PM_INVALID_ARG);
+  if (!(e > 0.0) || ch < 0.0 || !(a11 * a22 - a12 * a12 > 0.0) || !(a11 > 0.0)) {
+    atomicExch(err, PM_INVALID_ARG);
     return;
   }
   const double k = ch * exp(-s);
@@ -150,316 +149,6 @@ __global__ void k_assemble(int n, int kind, const int* __restrict__ perm, const 
   if (val32) val32[diagpos[i]] = (float)diag;
   if (dinv) dinv[i] = 1.0 / diag;
   if (b_lift) b_lift[old] = (lift[0] + lift[1]) + lift[2];
-}
-
-// ---------------------------------------------------------------------------
-// Solver kernels
-// ---------------------------------------------------------------------------
-
-// Difference-form rows from the float64 CSR: c_i = row sum, w = -off-diagonals
-// padded to three slots (padding: w = 0 pointing at the row itself), d' = c +
-// sum w evaluated from the stored (rounded) values, which is the Jacobi
-// diagonal the iteration uses.
-template <typename W, typename I>
-__global__ void k_prep_ell(int n, const int* __restrict__ rp, const int* __restrict__ col,
-                           const double* __restrict__ val, W* __restrict__ c, W* __restrict__ w,
-                           I* __restrict__ idx, double* __restrict__ dp, State* st) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double sum = 0.0;
-  bool finite_all = true;
-  W wv[3] = {W(0), W(0), W(0)};
-  I iv[3];
-  const I self = sizeof(I) == 2 ? I(0) : I(i);
-  iv[0] = iv[1] = iv[2] = self;
-  int nk = 0;
-  for (int k = rp[i]; k < rp[i + 1]; ++k) {
-    const double a = val[k];
-    finite_all = finite_all && isfinite(a);
-    sum += a;
-    const int j = col[k];
-    if (j != i && nk < 3) {
-      wv[nk] = (W)(-a);
-      iv[nk] = sizeof(I) == 2 ? I(j - i) : I(j);
-      ++nk;
-    }
-  }
-  const W cw = (W)sum;
-  c[i] = cw;
-  double d = (double)cw;
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    w[(size_t)k * n + i] = wv[k];
-    idx[(size_t)k * n + i] = iv[k];
-    d += (double)wv[k];
-  }
-  dp[i] = d;
-  if (!finite_all) atomicExch(&st->err, PM_NONFINITE);
-  else if (!(d > 0.0)) atomicExch(&st->err, PM_INVALID_ARG);
-}
-
-// b and x0 into the renumbered order; partials of ||b||^2 and ||x0||^2.
-template <typename V>
-__global__ void __launch_bounds__(1024) k_gather_in(int n, int rpb, const int* __restrict__ perm,
-                                                   const double* __restrict__ b,
-                                                   const double* __restrict__ x, int x0_zero,
-                                                   double* __restrict__ b64,
-                                                   double* __restrict__ x64,
-                                                   double* __restrict__ xlo, V* __restrict__ xacc,
-                                                   double* __restrict__ part) {
-  const int lb = xcd_block(blockIdx.x, gridDim.x);
-  const int r0 = lb * rpb, r1 = min(n, r0 + rpb);
-  double acc[2] = {0.0, 0.0};
-  for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
-    const int o = perm[i];
-    const double bi = b[o];
-    const double xi = x0_zero ? 0.0 : x[o];
-    b64[i] = bi;
-    x64[i] = xi;
-    xlo[i] = 0.0;
-    xacc[i] = V(0);
-    acc[0] += bi * bi;
-    acc[1] += xi * xi;
-  }
-  block_partial<2>(acc, part + 2 * (size_t)blockIdx.x);
-}
-
-// One block: ||b||, the tolerance, input checks.
-__global__ void k_start(const double* __restrict__ part, int nb, double tol, State* st) {
-  double s[2];
-  sum_partials<2>(part, nb, s);
-  if (threadIdx.x != 0) return;
-  st->bnorm2 = s[0];
-  st->tol2 = tol * tol * s[0];
-  if (st->err != 0) {
-    st->status = st->err;
-    st->done = 1;
-  } else if (!isfinite(s[0]) || !isfinite(s[1])) {
-    st->status = PM_NONFINITE;
-    st->done = 1;
-  } else if (s[0] == 0.0) {
-    st->status = PM_OK;
-    st->res2 = 0.0;
-    st->done = 2;  // zero right-hand side: the solution is 0
-  }
-}
-
-// True residuals from the float64 CSR with error-free transformations, for the
-// returned vector x_hi (stopping test) and for x_hi + x_lo (replacement);
-// partials of ||r_hi||^2, z.D'z and || |A||x_hi| ||^2 (rounding-floor estimate).
-//   mode 0 (start):   z = r_dd/d', p = z
-//   mode 1 (replace): z = r_dd/d'
-//   mode 2 (final):   norms only; runs even after the stop flag is set
-template <typename V>
-__global__ void __launch_bounds__(1024) k_resid(int n, int rpb, int mode, const int* __restrict__ rp,
-                                               const int* __restrict__ col,
-                                               const double* __restrict__ val,
-                                               const double* __restrict__ b64,
-                                               const double* __restrict__ x64,
-                                               const double* __restrict__ xlo,
-                                               const double* __restrict__ dp, V* __restrict__ z,
-                                               V* __restrict__ p, double* __restrict__ part,
-                                               const State* st) {
-  if (mode != 2 && st->done) return;
-  const int lb = xcd_block(blockIdx.x, gridDim.x);
-  const int r0 = lb * rpb, r1 = min(n, r0 + rpb);
-  double acc[3] = {0.0, 0.0, 0.0};
-  for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
-    double rh, rd, ax;
-    residual_row(b64[i], val, col, x64, xlo, rp[i], rp[i + 1], rh, rd, ax);
-    acc[0] += rh * rh;
-    acc[2] += ax * ax;
-    if (mode != 2) {
-      const double d = dp[i];
-      const V zv = (V)(rd / d);
-      z[i] = zv;
-      if (mode == 0) p[i] = zv;
-      const double zd = (double)zv;
-      acc[1] += d * zd * zd;
-    }
-  }
-  block_partial<3>(acc, part + 3 * (size_t)blockIdx.x);
-}
-
-// One block after k_resid: the convergence test on the returned vector, the
-// stagnation test (the residual norm has not halved for stag_checks
-// replacement points although it is within 1000x of the tolerance or of the
-// rounding floor u*|| |A||x| ||), and the scalars for the search direction.
-__global__ void k_check(int mode, const double* __restrict__ part, int nb, State* st) {
-  if (mode != 2 && st->done) return;
-  double s[3];
-  sum_partials<3>(part, nb, s);
-  if (threadIdx.x != 0) return;
-  st->res2 = s[0];
-  if (mode == 2) return;
-  if (!isfinite(s[0])) {
-    st->status = PM_NONFINITE;
-    st->done = 1;
-  } else if (s[0] <= st->tol2) {
-    st->status = PM_OK;
-    st->done = 1;
-  } else if (mode == 0) {
-    st->rho = s[1];
-    st->best_res2 = s[0];
-    st->stall = 0;
-  } else {
-    if (s[0] < 0.25 * st->best_res2) {
-      st->best_res2 = s[0];
-      st->stall = 0;
-    } else {
-      st->stall += 1;
-    }
-    const double floor2 = 0x1p-106 * s[2];
-    if (st->best_res2 < 1e6 * fmax(st->tol2, floor2) && st->stall >= st->stag_checks) {
-      st->status = PM_STAGNATED;
-      st->done = 1;
-    } else {
-      st->beta = s[1] / st->rho;
-      st->rho = s[1];
-    }
-  }
-}
-
-// p = z + beta p after a replacement.
-template <typename V>
-__global__ void __launch_bounds__(1024) k_pdir(int n, int rpb, const V* __restrict__ z,
-                                              V* __restrict__ p, const State* st) {
-  if (st->done) return;
-  const double b = st->beta;
-  const int lb = xcd_block(blockIdx.x, gridDim.x);
-  const int r0 = lb * rpb, r1 = min(n, r0 + rpb);
-  for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x) p[i] = (V)((double)z[i] + b * (double)p[i]);
-}
-
-// q~ = D'^{-1} A p (difference form) and, with q = D' q~ as stored, the block
-// partials of  s0 = p.q,  s1 = z.q (= q.D'^{-1} r),  s2 = q.D'^{-1} q,
-// s3 = z.D' z (= rho).
-template <typename V, typename W, typename I>
-__global__ void __launch_bounds__(1024) k_spmv(int n, int rpb, const W* __restrict__ c,
-                                              const W* __restrict__ w, const I* __restrict__ idx,
-                                              const V* __restrict__ p, const V* __restrict__ z,
-                                              V* __restrict__ q, double* __restrict__ part,
-                                              State* st) {
-  if (st->done) return;
-  const int lb = xcd_block(blockIdx.x, gridDim.x);
-  const int r0 = lb * rpb, r1 = min(n, r0 + rpb);
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
-    const W w0 = w[i], w1 = w[(size_t)n + i], w2 = w[2 * (size_t)n + i];
-    const int j0 = col_of<I>(i, idx[i]);
-    const int j1 = col_of<I>(i, idx[(size_t)n + i]);
-    const int j2 = col_of<I>(i, idx[2 * (size_t)n + i]);
-    const double pi = (double)p[i];
-    const double p0 = (double)p[j0], p1 = (double)p[j1], p2 = (double)p[j2];
-    const double ci = (double)c[i];
-    double y = ci * pi;
-    y += (double)w0 * (pi - p0);
-    y += (double)w1 * (pi - p1);
-    y += (double)w2 * (pi - p2);
-    const double d = ((ci + (double)w0) + (double)w1) + (double)w2;
-    const V qv = (V)(y / d);
-    q[i] = qv;
-    const double qd = (double)qv, zi = (double)z[i];
-    const double dq = d * qd;
-    acc[0] += pi * dq;
-    acc[1] += zi * dq;
-    acc[2] += qd * dq;
-    acc[3] += d * zi * zi;
-  }
-  block_partial<4>(acc, part + 4 * (size_t)blockIdx.x);
-  if (blockIdx.x == 0 && threadIdx.x == 0) st->iter_pending = st->iter + 1;
-}
-
-// Every block reduces the product's partials (same order, same result):
-// alpha = rho / p.q, the next rho by its recurrence anchored on the exact rho,
-// beta = rho_next / rho; then
-//   FLUSH = false:  x_acc += alpha p;  z -= alpha q~;  p = z + beta p
-//   FLUSH = true :  (x_hi, x_lo) += x_acc + alpha p; x_acc = 0  (replacement
-//                   iteration: z and p are rebuilt from the true residual)
-// Block 0 records the scalars and the iteration count, or the stop status.
-// `scale` multiplies alpha and beta (1 in solves; 0 when timing the kernel).
-template <typename V, bool FLUSH>
-__global__ void __launch_bounds__(1024) k_update(int n, int rpb, V* __restrict__ xacc,
-                                                V* __restrict__ p, V* __restrict__ z,
-                                                const V* __restrict__ q, double* __restrict__ x64,
-                                                double* __restrict__ xlo,
-                                                const double* __restrict__ part, int nbp,
-                                                double scale, State* st) {
-  if (st->done) return;
-  double s[4];
-  sum_partials<4>(part, nbp, s);
-  const int k = st->iter_pending;
-  const double pq = s[0], rho = s[3];
-  int stop = 0;
-  if (k > st->max_it) stop = PM_MAXIT;
-  else if (rho == 0.0) stop = 100;  // exact zero residual in the recurrence
-  else if (!(pq > 0.0) || !isfinite(pq) || !isfinite(rho)) stop = PM_BREAKDOWN;
-  if (stop) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      st->status = stop == 100 ? PM_OK : stop;
-      st->done = 1;
-    }
-    return;
-  }
-  const double a = rho / pq;
-  const double rn = rho - 2.0 * a * s[1] + a * a * s[2];
-  const double be = rn / rho;
-  const double as = a * scale, bs = be * scale;
-  const int lb = xcd_block(blockIdx.x, gridDim.x);
-  const int r0 = lb * rpb, r1 = min(n, r0 + rpb);
-  for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
-    const double pi = (double)p[i];
-    if (FLUSH) {
-      const double xi = (double)xacc[i] + as * pi;
-      double hi = x64[i], lo = xlo[i];
-      dd_add(hi, lo, xi);
-      x64[i] = hi;
-      xlo[i] = lo;
-      xacc[i] = V(0);
-    } else {
-      xacc[i] = (V)((double)xacc[i] + as * pi);
-      const V zv = (V)((double)z[i] - as * (double)q[i]);
-      z[i] = zv;
-      p[i] = (V)((double)zv + bs * pi);
-    }
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    st->alpha = a;
-    st->beta = be;
-    st->rho = rho;
-    st->iter = k;
-  }
-}
-
-// End of solve: fold any pending increments (limit or breakdown mid-chunk).
-template <typename V>
-__global__ void k_flush(int n, V* __restrict__ xacc, double* __restrict__ x64,
-                        double* __restrict__ xlo) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double hi = x64[i], lo = xlo[i];
-  dd_add(hi, lo, (double)xacc[i]);
-  x64[i] = hi;
-  xlo[i] = lo;
-  xacc[i] = V(0);
-}
-
-__global__ void k_scatter_out(int n, const int* __restrict__ perm, const double* __restrict__ x64,
-                              double* __restrict__ x, const State* st) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  x[perm[i]] = st->done == 2 ? 0.0 : x64[i];
-}
-
-// Timing support: make the iteration kernels run again on a finished state
-// (k_update is then launched with scale 0, which leaves the vectors unchanged).
-__global__ void k_timing_state(State* st) {
-  st->done = 0;
-  st->status = PM_OK;
-  st->max_it = INT_MAX;
-  st->iter = 0;
-  st->iter_pending = 1;
-  st->tol2 = -1.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -547,31 +236,17 @@ struct pm_mesh {
   HostStructure hs;
   int device = 0;
   int32_t n = 0, nnz = 0;
-  int index_bits = 32;
   // structure, renumbered order
   int32_t *perm = nullptr, *row_ptr = nullptr, *col = nullptr;
   int32_t *nb = nullptr, *pos = nullptr, *diagpos = nullptr;  // nb/pos: [3][n]
   int8_t* tag = nullptr;                                       // [3][n]
   double *T = nullptr, *tx = nullptr, *ty = nullptr, *area = nullptr;
-  // assembly scratch
+  // assembly scratch and its input-check flag
   double *X11 = nullptr, *X12 = nullptr, *X22 = nullptr, *M11 = nullptr, *M22 = nullptr;
-  // solver workspace (sized for float64 / int32; float32 runs use the front part)
-  void *ell_c = nullptr, *ell_w = nullptr, *ell_idx = nullptr;
-  double *dp = nullptr, *x64 = nullptr, *xlo = nullptr, *b64 = nullptr;
-  void *xacc = nullptr, *p = nullptr, *z = nullptr, *q = nullptr;
-  double* part = nullptr;   // per-block partials of the product / start kernels
-  double* part2 = nullptr;  // per-block partials of the residual kernel
-  State* st = nullptr;
-  State* h_st = nullptr;  // pinned, 3 slots
-  hipStream_t cap = nullptr;
-  hipEvent_t ev[2] = {nullptr, nullptr};
-  hipEvent_t tev[2] = {nullptr, nullptr};
-  hipGraphExec_t graph = nullptr;
-  int g_prec = -1, g_m = -1, g_grid = -1, g_block = -1;
-  const double* g_val = nullptr;
-  // launch shape and matrix of the last solve (for pm_time_kernel)
-  int last_prec = -1, last_grid = 0, last_block = 256, last_rpb = 0;
-  const double* last_val = nullptr;
+  int32_t* asm_err = nullptr;
+  int32_t* h_err = nullptr;  // pinned
+  // the solver workspace (a set with one system)
+  SolveSet set;
   std::vector<void*> allocs;
 };
 
@@ -596,174 +271,21 @@ int dalloc(pm_mesh* m, T** ptr, size_t count) {
 
 void free_mesh(pm_mesh* m) {
   if (!m) return;
-  if (m->graph) (void)hipGraphExecDestroy(m->graph);
+  set_free(m->set);
   for (void* p : m->allocs) (void)hipFree(p);
-  if (m->h_st) (void)hipHostFree(m->h_st);
-  for (auto& e : m->ev)
-    if (e) (void)hipEventDestroy(e);
-  for (auto& e : m->tev)
-    if (e) (void)hipEventDestroy(e);
-  if (m->cap) (void)hipStreamDestroy(m->cap);
+  if (m->h_err) (void)hipHostFree(m->h_err);
   delete m;
-}
-
-struct Launch {
-  int grid, block, rpb;
-};
-
-Launch launch_shape(int n, const pm_opts* o) {
-  Launch L;
-  L.block = (o && o->block > 0) ? o->block : 256;
-  L.block = std::min(1024, std::max(64, (L.block / 64) * 64));
-  int g = (o && o->grid > 0) ? o->grid : (n + 2 * L.block - 1) / (2 * L.block);
-  g = std::max(1, std::min(g, kMaxBlocks));
-  L.rpb = (n + g - 1) / g;
-  L.grid = (n + L.rpb - 1) / L.rpb;
-  return L;
 }
 
 inline int blocks_for(int n, int b) { return (n + b - 1) / b; }
 
 }  // namespace
 
-// ---------------------------------------------------------------------------
-// The iteration for one precision / index width
-// ---------------------------------------------------------------------------
-template <typename V, typename W, typename I>
-struct Solver {
-  static void prep(pm_mesh* m, const double* val64, hipStream_t s) {
-    k_prep_ell<W, I><<<blocks_for(m->n, 256), 256, 0, s>>>(
-        m->n, m->row_ptr, m->col, val64, (W*)m->ell_c, (W*)m->ell_w, (I*)m->ell_idx, m->dp, m->st);
-  }
-  static void start(pm_mesh* m, const Launch& L, const double* b, const double* x, int x0_zero,
-                    double tol, const double* val64, hipStream_t s) {
-    k_gather_in<V><<<L.grid, L.block, 0, s>>>(m->n, L.rpb, m->perm, b, x, x0_zero, m->b64, m->x64,
-                                              m->xlo, (V*)m->xacc, m->part);
-    k_start<<<1, 256, 0, s>>>(m->part, L.grid, tol, m->st);
-    resid(m, L, 0, val64, s);
-  }
-  static void spmv(pm_mesh* m, const Launch& L, hipStream_t s) {
-    k_spmv<V, W, I><<<L.grid, L.block, 0, s>>>(m->n, L.rpb, (const W*)m->ell_c, (const W*)m->ell_w,
-                                               (const I*)m->ell_idx, (const V*)m->p,
-                                               (const V*)m->z, (V*)m->q, m->part, m->st);
-  }
-  template <bool FLUSH>
-  static void update(pm_mesh* m, const Launch& L, hipStream_t s, double scale = 1.0) {
-    k_update<V, FLUSH><<<L.grid, L.block, 0, s>>>(m->n, L.rpb, (V*)m->xacc, (V*)m->p, (V*)m->z,
-                                                  (const V*)m->q, m->x64, m->xlo, m->part, L.grid,
-                                                  scale, m->st);
-  }
-  static void resid(pm_mesh* m, const Launch& L, int mode, const double* val64, hipStream_t s) {
-    k_resid<V><<<L.grid, L.block, 0, s>>>(m->n, L.rpb, mode, m->row_ptr, m->col, val64, m->b64,
-                                          m->x64, m->xlo, m->dp, (V*)m->z, (V*)m->p, m->part2,
-                                          m->st);
-    k_check<<<1, 256, 0, s>>>(mode, m->part2, L.grid, m->st);
-  }
-  // one chunk of m iterations ending with a replacement
-  static void chunk(pm_mesh* m, const Launch& L, int mrep, const double* val64, hipStream_t s) {
-    for (int it = 0; it < mrep - 1; ++it) {
-      spmv(m, L, s);
-      update<false>(m, L, s);
-    }
-    spmv(m, L, s);
-    update<true>(m, L, s);
-    resid(m, L, 1, val64, s);
-    k_pdir<V><<<L.grid, L.block, 0, s>>>(m->n, L.rpb, (const V*)m->z, (V*)m->p, m->st);
-  }
-  static void finish(pm_mesh* m, const Launch& L, const double* val64, double* x, hipStream_t s) {
-    k_flush<V><<<blocks_for(m->n, 256), 256, 0, s>>>(m->n, (V*)m->xacc, m->x64, m->xlo);
-    resid(m, L, 2, val64, s);
-    k_scatter_out<<<blocks_for(m->n, 256), 256, 0, s>>>(m->n, m->perm, m->x64, x, m->st);
-  }
-};
-
 namespace {
-
-// The graph of one chunk reads val64 through its kernel arguments, so it is
-// rebuilt when the matrix pointer changes.
-struct ChunkKey {
-  int prec, m, grid, block;
-  const double* val;
-};
-
-template <typename V, typename W, typename I>
-int run_solve(pm_mesh* m, const double* val64, const double* b, double* x, const pm_opts& o,
-              pm_info* info, hipStream_t s) {
-  using S = Solver<V, W, I>;
-  const Launch L = launch_shape(m->n, &o);
-  m->last_prec = o.precision;
-  m->last_grid = L.grid;
-  m->last_block = L.block;
-  m->last_rpb = L.rpb;
-  m->last_val = val64;
-
-  State init{};
-  init.max_it = o.max_it;
-  init.stag_checks = o.stag_checks > 0 ? o.stag_checks : 40;
-  std::memcpy(&m->h_st[2], &init, sizeof(State));
-  PM_HIP(hipMemcpyAsync(m->st, &m->h_st[2], sizeof(State), hipMemcpyHostToDevice, s));
-  S::prep(m, val64, s);
-  S::start(m, L, b, x, o.x0_is_zero, o.tol, val64, s);
-  PM_HIP(hipGetLastError());
-
-  // (re)build the chunk graph (its kernels take val64 as an argument)
-  if (!m->graph || m->g_prec != o.precision || m->g_m != o.replace_every || m->g_grid != L.grid ||
-      m->g_block != L.block || m->g_val != val64) {
-    if (m->graph) {
-      (void)hipGraphExecDestroy(m->graph);
-      m->graph = nullptr;
-    }
-    hipGraph_t g = nullptr;
-    PM_HIP(hipStreamBeginCapture(m->cap, hipStreamCaptureModeThreadLocal));
-    S::chunk(m, L, o.replace_every, val64, m->cap);
-    PM_HIP(hipStreamEndCapture(m->cap, &g));
-    PM_HIP(hipGraphInstantiate(&m->graph, g, nullptr, nullptr, 0));
-    (void)hipGraphDestroy(g);
-    m->g_prec = o.precision;
-    m->g_m = o.replace_every;
-    m->g_grid = L.grid;
-    m->g_block = L.block;
-    m->g_val = val64;
-  }
-
-  // replay chunks; poll the stop flag one chunk behind so the GPU stays busy
-  const long max_chunks = (long)o.max_it / o.replace_every + 3;
-  PM_HIP(hipMemcpyAsync(&m->h_st[0], m->st, sizeof(State), hipMemcpyDeviceToHost, s));
-  PM_HIP(hipEventRecord(m->ev[0], s));
-  PM_HIP(hipEventSynchronize(m->ev[0]));
-  bool stop = m->h_st[0].done != 0;
-  long c = 0;
-  while (!stop && c < max_chunks) {
-    PM_HIP(hipGraphLaunch(m->graph, s));
-    const int slot = (int)(c & 1);
-    PM_HIP(hipMemcpyAsync(&m->h_st[slot], m->st, sizeof(State), hipMemcpyDeviceToHost, s));
-    PM_HIP(hipEventRecord(m->ev[slot], s));
-    if (c >= 1) {
-      PM_HIP(hipEventSynchronize(m->ev[slot ^ 1]));
-      if (m->h_st[slot ^ 1].done) stop = true;
-    }
-    ++c;
-  }
-  S::finish(m, L, val64, x, s);
-  PM_HIP(hipGetLastError());
-  PM_HIP(hipMemcpyAsync(&m->h_st[0], m->st, sizeof(State), hipMemcpyDeviceToHost, s));
-  PM_HIP(hipStreamSynchronize(s));
-  const State& f = m->h_st[0];
-  int status = f.done ? f.status : PM_MAXIT;
-  if (f.err) status = f.err;
-  if (info) {
-    info->iters = f.iter;
-    info->status = status;
-    info->bnorm = std::sqrt(f.bnorm2);
-    info->rel_res_true = f.bnorm2 > 0 ? std::sqrt(f.res2 / f.bnorm2) : 0.0;
-  }
-  if (status < 0) set_error(status, "pcg_solve stopped with an error status");
-  return status;
-}
 
 int check_opts(const pm_opts& o) {
   if (!(o.tol > 0.0) || o.max_it < 0 || o.replace_every < 1 ||
-      (o.precision != PM_FP64 && o.precision != PM_MIXED)) {
+      (o.precision != PM_FP64 && o.precision != PM_MIXED) || o.tile_rows < 0 || o.block < 0) {
     set_error(PM_INVALID_ARG, "invalid solver options");
     return PM_INVALID_ARG;
   }
@@ -785,7 +307,7 @@ void pm_opts_default(pm_opts* o) {
   o->replace_every = 50;
   o->x0_is_zero = 1;
   o->block = 0;
-  o->grid = 0;
+  o->tile_rows = 0;
   o->stag_checks = 40;
 }
 
@@ -849,7 +371,6 @@ int pm_mesh_create(int32_t n_nodes, const double* xy, int32_t n_cells, const int
   const size_t n = hs.n;
   m->n = hs.n;
   m->nnz = hs.stats.nnz;
-  m->index_bits = hs.stats.index_bits;
   (void)hipGetDevice(&m->device);
 
   // per-side arrays in the renumbered order, side-major
@@ -897,29 +418,7 @@ int pm_mesh_create(int32_t n_nodes, const double* xy, int32_t n_cells, const int
   ALLOC(m->X22, n);
   ALLOC(m->M11, n);
   ALLOC(m->M22, n);
-  double* tmp;
-  ALLOC(tmp, n);
-  m->ell_c = tmp;
-  ALLOC(tmp, 3 * n);
-  m->ell_w = tmp;
-  int32_t* itmp;
-  ALLOC(itmp, 3 * n);
-  m->ell_idx = itmp;
-  ALLOC(m->dp, n);
-  ALLOC(m->x64, n);
-  ALLOC(m->xlo, n);
-  ALLOC(m->b64, n);
-  ALLOC(tmp, n);
-  m->xacc = tmp;
-  ALLOC(tmp, n);
-  m->p = tmp;
-  ALLOC(tmp, n);
-  m->z = tmp;
-  ALLOC(tmp, n);
-  m->q = tmp;
-  ALLOC(m->part, (size_t)kMaxBlocks * 4);
-  ALLOC(m->part2, (size_t)kMaxBlocks * 4);
-  ALLOC(m->st, 1);
+  ALLOC(m->asm_err, 1);
 #undef ALLOC
   auto fail = [&](hipError_t e, const char* what) {
     set_error(PM_HIP_ERROR, std::string(what) + ": " + hipGetErrorString(e));
@@ -927,15 +426,8 @@ int pm_mesh_create(int32_t n_nodes, const double* xy, int32_t n_cells, const int
     return PM_HIP_ERROR;
   };
   hipError_t e;
-  if ((e = hipHostMalloc((void**)&m->h_st, 3 * sizeof(State), hipHostMallocDefault)) != hipSuccess)
+  if ((e = hipHostMalloc((void**)&m->h_err, sizeof(int32_t), hipHostMallocDefault)) != hipSuccess)
     return fail(e, "hipHostMalloc");
-  if ((e = hipStreamCreateWithFlags(&m->cap, hipStreamNonBlocking)) != hipSuccess)
-    return fail(e, "hipStreamCreate");
-  for (auto& ev : m->ev)
-    if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess)
-      return fail(e, "hipEventCreate");
-  for (auto& ev : m->tev)
-    if ((e = hipEventCreate(&ev)) != hipSuccess) return fail(e, "hipEventCreate");
   struct Up {
     void* d;
     const void* h;
@@ -951,6 +443,11 @@ int pm_mesh_create(int32_t n_nodes, const double* xy, int32_t n_cells, const int
   for (const Up& u : ups)
     if ((e = hipMemcpy(u.d, u.h, u.bytes, hipMemcpyHostToDevice)) != hipSuccess)
       return fail(e, "hipMemcpy");
+  if ((r = set_init(m->set, std::vector<int>{m->n}, m->nnz, hs.stats.index_bits, m->perm,
+                    m->row_ptr, m->col)) != PM_OK) {
+    free_mesh(m);
+    return r;
+  }
   *out = m;
   return PM_OK;
 }
@@ -991,20 +488,20 @@ int assemble_corrector(pm_mesh* m, int32_t kind, const pm_cell_params* prm, doub
         set_error(PM_SINGULAR, "CP2: a mesh component has no CP2 Dirichlet side");
         return PM_SINGULAR;
       }
-  PM_HIP(hipMemsetAsync(&m->st->err, 0, sizeof(int32_t), s));
+  PM_HIP(hipMemsetAsync(m->asm_err, 0, sizeof(int32_t), s));
   const int nbk = blocks_for(m->n, 256);
   k_cell_tensors<<<nbk, 256, 0, s>>>(m->n, m->perm, prm->eps, prm->logk, prm->chi, prm->g11,
                                      prm->g12, prm->g22, nu, dt, m->X11, m->X12, m->X22, m->M11,
-                                     m->M22, m->st);
+                                     m->M22, m->asm_err);
   k_assemble<<<nbk, 256, 0, s>>>(m->n, kind, m->perm, m->nb, m->pos, m->diagpos, m->tag, m->T,
                                  m->tx, m->ty, m->area, m->X11, m->X12, m->X22, m->M11, m->M22, nu,
                                  g, val64, val32, dinv, b_lift);
   PM_HIP(hipGetLastError());
-  PM_HIP(hipMemcpyAsync(&m->h_st[2].err, &m->st->err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  PM_HIP(hipMemcpyAsync(m->h_err, m->asm_err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   PM_HIP(hipStreamSynchronize(s));
-  if (m->h_st[2].err) {
-    set_error(m->h_st[2].err, "assemble_corrector: invalid or non-finite cell parameters");
-    return m->h_st[2].err;
+  if (*m->h_err) {
+    set_error(*m->h_err, "assemble_corrector: invalid or non-finite cell parameters");
+    return *m->h_err;
   }
   return PM_OK;
 }
@@ -1019,12 +516,9 @@ int pcg_solve(pm_mesh* m, const double* val64, const double* b, double* x, const
   pm_opts_default(&o);
   if (opts) o = *opts;
   if (int r = check_opts(o)) return r;
-  const bool i16 = m->index_bits == 16;
-  if (o.precision == PM_FP64)
-    return i16 ? run_solve<double, double, int16_t>(m, val64, b, x, o, info, s)
-               : run_solve<double, double, int32_t>(m, val64, b, x, o, info, s);
-  return i16 ? run_solve<float, float, int16_t>(m, val64, b, x, o, info, s)
-             : run_solve<float, float, int32_t>(m, val64, b, x, o, info, s);
+  const int st = set_solve(m->set, val64, b, x, o, info, s);
+  if (st < 0) set_error(st, "pcg_solve stopped with an error status");
+  return st;
 }
 
 int pcg_adjoint(pm_mesh* m, int32_t kind, const pm_cell_params* prm, double nu, double dt,
@@ -1052,48 +546,11 @@ int pcg_adjoint(pm_mesh* m, int32_t kind, const pm_cell_params* prm, double nu, 
 
 int pm_time_kernel(pm_mesh* m, int32_t which, int32_t n_launch, hipStream_t s, double* ms,
                    double* bytes) {
-  if (!m || m->last_prec < 0 || which < 0 || which > 2 || n_launch < 1) {
-    set_error(PM_INVALID_ARG, "pm_time_kernel: no solve to time or bad kernel id");
+  if (!m) {
+    set_error(PM_INVALID_ARG, "pm_time_kernel: null mesh");
     return PM_INVALID_ARG;
   }
-  pm_opts o;
-  pm_opts_default(&o);
-  o.grid = m->last_grid;
-  o.block = m->last_block;
-  const Launch L = launch_shape(m->n, &o);
-  const bool f64 = m->last_prec == PM_FP64, i16 = m->index_bits == 16;
-  const double sv = f64 ? 8 : 4, sw = sv, si = i16 ? 2 : 4, n = m->n;
-  k_timing_state<<<1, 1, 0, s>>>(m->st);
-  PM_HIP(hipEventRecord(m->tev[0], s));
-  for (int r = 0; r < n_launch; ++r) {
-    if (which == 0) {
-      if (f64) {
-        if (i16) Solver<double, double, int16_t>::spmv(m, L, s);
-        else Solver<double, double, int32_t>::spmv(m, L, s);
-      } else {
-        if (i16) Solver<float, float, int16_t>::spmv(m, L, s);
-        else Solver<float, float, int32_t>::spmv(m, L, s);
-      }
-    } else if (which == 1) {
-      if (f64) Solver<double, double, int32_t>::update<false>(m, L, s, 0.0);
-      else Solver<float, float, int32_t>::update<false>(m, L, s, 0.0);
-    } else {
-      if (f64) Solver<double, double, int32_t>::resid(m, L, 2, m->last_val, s);
-      else Solver<float, float, int32_t>::resid(m, L, 2, m->last_val, s);
-    }
-  }
-  PM_HIP(hipEventRecord(m->tev[1], s));
-  PM_HIP(hipGetLastError());
-  PM_HIP(hipEventSynchronize(m->tev[1]));
-  float t = 0.f;
-  PM_HIP(hipEventElapsedTime(&t, m->tev[0], m->tev[1]));
-  if (ms) *ms = (double)t / n_launch;
-  if (bytes) {
-    if (which == 0) *bytes = n * (4 * sw + 3 * si + 3 * sv);
-    else if (which == 1) *bytes = n * 7 * sv;
-    else *bytes = 12.0 * m->nnz + 4.0 * (n + 1) + 16.0 * n;
-  }
-  return PM_OK;
+  return set_time_kernel(m->set, which, n_launch, s, ms, bytes);
 }
 
 }  // extern "C"

@@ -1,0 +1,71 @@
+// Internal: the PCG driver shared by pcg_solve (one system) and
+// pcg_solve_batched (several systems packed one after another).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "pm_internal.h"
+
+namespace pm {
+
+// Per-system solver state (device memory).
+struct SysState {
+  double alpha, beta, rho;  // current CG scalars
+  double bnorm2, tol2;      // ||b||^2 and tol^2 ||b||^2
+  double res2;              // last true residual ||b - A x_hi||^2
+  double best_res2;         // smallest res2 seen (stagnation test)
+  int32_t iter;             // completed iterations
+  int32_t iter_pending;     // iteration the current product belongs to
+  int32_t max_it, stag_checks;
+  int32_t done;             // 0 running, 1 stopped, 2 zero right-hand side
+  int32_t status;           // PM_* status once stopped
+  int32_t stall;            // replacement points since res2 last halved
+  int32_t err;              // input check failure found by the preparation kernel
+};
+
+// A set of one or more independent systems laid out one after another.
+// Rows of system s occupy [row0[s], row0[s+1]); the CSR arrays are the packed
+// matrices (columns are global row indices); perm maps each packed row to the
+// packed cell-order index of the caller's vectors.
+struct SolveSet {
+  int N = 0, n_sys = 0;
+  int64_t nnz = 0;
+  int index_bits = 32;
+  std::vector<int> row0;  // host, n_sys + 1
+  const int* perm = nullptr;
+  const int* rp = nullptr;
+  const int* col = nullptr;
+  // work tiles (rows of one system each), rebuilt when the tile size changes
+  int tile_rows = 0, n_tiles = 0, max_tiles = 0;
+  int *tile_sys = nullptr, *tile_r0 = nullptr, *tile_r1 = nullptr, *sys_tile0 = nullptr;
+  // workspace: difference-form rows, vectors, partials, states
+  void *c = nullptr, *w = nullptr, *idx = nullptr;
+  double *dp = nullptr, *x64 = nullptr, *xlo = nullptr, *b64 = nullptr;
+  void *xacc = nullptr, *p = nullptr, *z = nullptr, *q = nullptr;
+  double *part4 = nullptr, *part3 = nullptr;
+  SysState* ss = nullptr;
+  SysState* h_ss = nullptr;  // pinned, 3 slots of n_sys states
+  hipStream_t cap = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipEvent_t tev[2] = {nullptr, nullptr};
+  hipGraphExec_t graph = nullptr;
+  int g_prec = -1, g_m = -1, g_tile = -1, g_block = -1;
+  const double* g_val = nullptr;
+  // last solve, for the timing hook
+  int last_prec = -1, last_tile = 0, last_block = 256;
+  const double* last_val = nullptr;
+  std::vector<void*> allocs;
+};
+
+int set_init(SolveSet& S, const std::vector<int>& rows_per_sys, int64_t nnz, int index_bits,
+             const int* perm, const int* rp, const int* col);
+void set_free(SolveSet& S);
+int set_solve(SolveSet& S, const double* val64, const double* b, double* x, const pm_opts& o,
+              pm_info* infos, hipStream_t s);
+int set_time_kernel(SolveSet& S, int which, int n_launch, hipStream_t s, double* ms,
+                    double* bytes);
+
+}  // namespace pm

@@ -159,8 +159,8 @@ def test_solves_are_deterministic_and_launch_shape_independent():
     x1, i1 = B().pcg_solve(c["mesh"], val, b)
     x2, i2 = B().pcg_solve(c["mesh"], val, b)
     assert torch.equal(x1, x2) and i1["iters"] == i2["iters"]
-    for grid in (1, 3, 17):
-        x3, i3 = B().pcg_solve(c["mesh"], val, b, grid=grid)
+    for tile in (256, 768, 4096):
+        x3, i3 = B().pcg_solve(c["mesh"], val, b, tile_rows=tile)
         assert i3["status"] == 0
         assert torch.linalg.norm(x3 - x1) <= 1e-9 * torch.linalg.norm(x1)
 
