@@ -105,12 +105,22 @@ typedef struct {
   int32_t replace_every; /* true-residual replacement period m (default 50); the
                             stopping test runs at these points */
   int32_t x0_is_zero;    /* 1: ignore x on entry and start from 0 */
-  int32_t block;         /* threads per block of the iteration kernels (0 = 256) */
-  int32_t tile_rows;     /* rows per work tile (one block each; >= 256); 0 = chosen
-                            by the built-in tuner and cached per problem shape */
-  int32_t stag_checks;   /* replacement points without the residual halving, once
-                            below 1000*max(tol*||b||, u*|| |A||x| ||), before
-                            PM_STAGNATED (default 40) */
+  int32_t block;         /* threads per block of the iteration kernels when
+                            tile_rows is given (0 = 256; rounded down to a
+                            multiple of 64, at most 512) */
+  int32_t tile_rows;     /* rows per work tile (one block each; >= 256); 0 = tile,
+                            block and rows per thread chosen by the built-in
+                            tuner, which times the fused iteration kernel on the
+                            first solve of a problem shape and precision */
+  int32_t stag_checks;   /* PM_STAGNATED once the best true residual is within
+                            100x of the rounding floor u*|| |A||x| || and has
+                            not halved for max(stag_checks * replace_every,
+                            k_best) iterations, k_best being the iteration of
+                            the last halving (default 40) */
+  int32_t iter_rows;     /* with tile_rows: rows per thread and trip of the fused
+                            iteration kernel (1, 2, or 4 in PM_MIXED; 0 = 1), or
+                            -1 for the split schedule (update kernel, then
+                            product kernel); ignored when the tuner decides */
 } pm_opts;
 
 typedef struct {
@@ -259,12 +269,29 @@ int pcg_adjoint(pm_mesh* mesh, int32_t kind, const pm_cell_params* params, doubl
  * on the state left by the last pcg_solve of this mesh (same precision and
  * launch shape) between two HIP events on `stream`, and returns the mean
  * duration in milliseconds and the bytes one launch must move.
- *   which  0: matrix-vector product with fused dot products
- *          1: vector update (x, z, p)
+ *   which  0: plain matrix-vector product with fused dot products (opens
+ *             each chunk of m iterations)
+ *          1: one iteration of the schedule in use: the fused kernel
+ *             (update of x, z, p and the product of the new direction with
+ *             its dot products in one launch), or on the split schedule the
+ *             update kernel followed by the product; timed with zero step
+ *             lengths, so the state does not change
  *          2: true-residual kernel (float64 CSR, compensated)
+ * Bytes per launch, n rows, vector/weight/index widths sv/sw/si:
+ *   0: n (4 sw + 3 si + 3 sv)
+ *   1: n (4 sw + 3 si + 8 sv) fused, n (4 sw + 3 si + 10 sv) split
+ *   2: 12 nnz + 4 (n + 1) + 24 n
  */
 int pm_time_kernel(pm_mesh* mesh, int32_t which, int32_t n_launch, hipStream_t stream,
                    double* ms_per_launch, double* bytes_per_launch);
+
+/*
+ * Launch shape of the last pcg_solve on this mesh: rows per tile, threads per
+ * block and rows per thread and trip of the fused iteration kernel, 0 for the
+ * split schedule (as chosen by the tuner or given in pm_opts).  Returns
+ * PM_INVALID_ARG before the first solve.
+ */
+int pm_last_launch(const pm_mesh* mesh, int32_t* tile_rows, int32_t* block, int32_t* rows);
 
 #ifdef __cplusplus
 }

@@ -41,7 +41,7 @@ class pm_opts(C.Structure):
     _fields_ = [
         ("tol", C.c_double), ("max_it", C.c_int32), ("precision", C.c_int32),
         ("replace_every", C.c_int32), ("x0_is_zero", C.c_int32), ("block", C.c_int32),
-        ("tile_rows", C.c_int32), ("stag_checks", C.c_int32),
+        ("tile_rows", C.c_int32), ("stag_checks", C.c_int32), ("iter_rows", C.c_int32),
     ]
 
 
@@ -87,6 +87,7 @@ def lib():
             "pcg_solve_batched": (C.c_int, [P, P, P, P, P, P, P]),
             "pcg_adjoint": (C.c_int, [P, I32, P, D, D, P, P, P, P, P, P, P, P, P, P]),
             "pm_time_kernel": (C.c_int, [P, I32, I32, P, P, P]),
+            "pm_last_launch": (C.c_int, [P, P, P, P]),
         }
         for name, (res, args) in sig.items():
             if hasattr(L, name):
@@ -221,12 +222,13 @@ def assemble_corrector(mesh: Mesh, kind: int, params: dict, nu: float, dt: float
 
 
 def make_opts(tol=1e-10, max_it=200000, precision=PM_FP64, replace_every=50, x0_is_zero=True,
-              block=0, tile_rows=0, stag_checks=40) -> pm_opts:
+              block=0, tile_rows=0, stag_checks=40, iter_rows=0) -> pm_opts:
     o = pm_opts()
     lib().pm_opts_default(C.addressof(o))
     o.tol, o.max_it, o.precision, o.replace_every = tol, max_it, precision, replace_every
     o.x0_is_zero, o.block, o.tile_rows = int(bool(x0_is_zero)), block, tile_rows
     o.stag_checks = stag_checks
+    o.iter_rows = iter_rows
     return o
 
 
@@ -315,9 +317,16 @@ def pm_time_kernel(mesh: Mesh, which: int, n_launch: int, stream=None):
     return ms.value, by.value
 
 
+def pm_last_launch(mesh: Mesh) -> dict:
+    """Launch shape (tile rows, block, rows per thread) of the last solve on `mesh`."""
+    v = [C.c_int32() for _ in range(3)]
+    _check(lib().pm_last_launch(mesh.handle, *[C.byref(x) for x in v]))
+    return {"tile_rows": v[0].value, "block": v[1].value, "rows": v[2].value}
+
+
 EXPORTED = [
     "pm_opts_default", "pm_status_string", "pm_last_error", "pm_structure_host", "pm_mesh_create",
     "pm_mesh_destroy", "pm_mesh_get_stats", "pm_mesh_export", "assemble_corrector", "pcg_solve",
     "pm_batch_create", "pm_batch_destroy", "pm_batch_offsets", "pcg_solve_batched", "pcg_adjoint",
-    "pm_time_kernel",
+    "pm_time_kernel", "pm_last_launch",
 ]

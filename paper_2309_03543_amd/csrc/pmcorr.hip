@@ -285,7 +285,9 @@ namespace {
 
 int check_opts(const pm_opts& o) {
   if (!(o.tol > 0.0) || o.max_it < 0 || o.replace_every < 1 ||
-      (o.precision != PM_FP64 && o.precision != PM_MIXED) || o.tile_rows < 0 || o.block < 0) {
+      (o.precision != PM_FP64 && o.precision != PM_MIXED) || o.tile_rows < 0 || o.block < 0 ||
+      !(o.iter_rows == -1 || o.iter_rows == 0 || o.iter_rows == 1 || o.iter_rows == 2 ||
+        (o.iter_rows == 4 && o.precision == PM_MIXED))) {
     set_error(PM_INVALID_ARG, "invalid solver options");
     return PM_INVALID_ARG;
   }
@@ -309,6 +311,7 @@ void pm_opts_default(pm_opts* o) {
   o->block = 0;
   o->tile_rows = 0;
   o->stag_checks = 40;
+  o->iter_rows = 0;
 }
 
 const char* pm_status_string(int s) {
@@ -551,6 +554,17 @@ int pm_time_kernel(pm_mesh* m, int32_t which, int32_t n_launch, hipStream_t s, d
     return PM_INVALID_ARG;
   }
   return set_time_kernel(m->set, which, n_launch, s, ms, bytes);
+}
+
+int pm_last_launch(const pm_mesh* m, int32_t* tile_rows, int32_t* block, int32_t* rows) {
+  if (!m || m->set.last_prec < 0) {
+    set_error(PM_INVALID_ARG, "pm_last_launch: null mesh or no solve yet");
+    return PM_INVALID_ARG;
+  }
+  if (tile_rows) *tile_rows = m->set.last_tile;
+  if (block) *block = m->set.last_block;
+  if (rows) *rows = m->set.last_rows;
+  return PM_OK;
 }
 
 }  // extern "C"

@@ -18,11 +18,12 @@ struct SysState {
   double res2;              // last true residual ||b - A x_hi||^2
   double best_res2;         // smallest res2 seen (stagnation test)
   int32_t iter;             // completed iterations
-  int32_t iter_pending;     // iteration the current product belongs to
-  int32_t max_it, stag_checks;
+  int32_t iter_base;        // completed iterations at the start of the current chunk
+  int32_t max_it;
+  int32_t stag_it;          // minimum stagnation window (stag_checks * m iterations)
   int32_t done;             // 0 running, 1 stopped, 2 zero right-hand side
   int32_t status;           // PM_* status once stopped
-  int32_t stall;            // replacement points since res2 last halved
+  int32_t k_best;           // iteration at which res2 last fell below best_res2 / 4
   int32_t err;              // input check failure found by the preparation kernel
 };
 
@@ -44,18 +45,19 @@ struct SolveSet {
   // workspace: difference-form rows, vectors, partials, states
   void *c = nullptr, *w = nullptr, *idx = nullptr;
   double *dp = nullptr, *x64 = nullptr, *xlo = nullptr, *b64 = nullptr;
-  void *xacc = nullptr, *p = nullptr, *z = nullptr, *q = nullptr;
-  double *part4 = nullptr, *part3 = nullptr;
+  void* xacc = nullptr;
+  void *p[2] = {nullptr, nullptr}, *z[2] = {nullptr, nullptr}, *q[2] = {nullptr, nullptr};
+  double *part[2] = {nullptr, nullptr}, *part3 = nullptr;
   SysState* ss = nullptr;
   SysState* h_ss = nullptr;  // pinned, 3 slots of n_sys states
   hipStream_t cap = nullptr;
   hipEvent_t ev[2] = {nullptr, nullptr};
   hipEvent_t tev[2] = {nullptr, nullptr};
   hipGraphExec_t graph = nullptr;
-  int g_prec = -1, g_m = -1, g_tile = -1, g_block = -1;
+  int g_prec = -1, g_m = -1, g_tile = -1, g_block = -1, g_rows = -1;
   const double* g_val = nullptr;
   // last solve, for the timing hook
-  int last_prec = -1, last_tile = 0, last_block = 256;
+  int last_prec = -1, last_tile = 0, last_block = 256, last_rows = 2;
   const double* last_val = nullptr;
   std::vector<void*> allocs;
 };

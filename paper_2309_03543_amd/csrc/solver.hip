@@ -1,19 +1,22 @@
 // Jacobi-preconditioned CG for one or several corrector systems (gfx950).
 //
 // Work is cut into tiles of consecutive rows of one system; one block of
-// threads owns a tile.  An iteration is two kernels:
-//   k_spmv    q~ = D'^{-1} A p in difference form, fused with the four dot
-//             products the iteration needs (per-tile partials)
-//   k_update  every block reduces its system's partials in a fixed order
-//             (identical result in every block), forms alpha and beta
-//             (recurrence for the next rho, anchored on the exact rho), and
-//             updates x_acc, z and p
-// Every m-th iteration the increments are folded into the double-double
-// solution and the residual is recomputed exactly from the float64 CSR
-// matrix (k_update<FLUSH>, k_resid, k_sys_check, k_pdir).  The kernel
-// boundaries are the only grid-wide synchronisation: no fences, no spin
-// waits.  Chunks of m iterations are captured once in a HIP graph and
-// replayed; a system whose test passes is masked out of later kernels.
+// threads owns a tile.  One kernel per iteration:
+//   k_iter    every block reduces its system's partials of the last product
+//             in a fixed order (identical result in every block), forms alpha
+//             and beta (recurrence for the next rho, anchored on the exact
+//             rho), updates x_acc, z and p of its rows, and applies A to the
+//             new p at once: the new p of a neighbour row is recomputed from
+//             that row's old p, z and q~ with the same operations its owner
+//             uses, so no grid-wide wait separates the update from the
+//             product.  p, z and q~ alternate between two buffers.
+// A chunk of m iterations opens with a plain product (k_spmv) and ends with
+// the m-th update folding the increments into the double-double solution
+// (k_update_flush), an exact float64 residual from the CSR matrix (k_resid,
+// k_sys_check) and the new direction (k_pdir).  The kernel boundaries are the
+// only grid-wide synchronisation: no fences, no spin waits.  Chunks are
+// captured once in a HIP graph and replayed; a system whose test passes is
+// masked out of later kernels.
 //
 // Difference form: row i is stored as c_i = sum_j a_ij (its mass or
 // Dirichlet part) and w_ij = -a_ij, and (A p)_i = c_i p_i + sum_j w_ij (p_i -
@@ -61,11 +64,11 @@ struct SetArgs {
   double* xlo;
   double* b64;
   V* xacc;
-  V* p;
-  V* z;
-  V* q;
-  double* part4;  // [tile][4]
-  double* part3;  // [tile][4], residual partials
+  V* p[2];        // ping-pong direction, residual/D' and D'^{-1} A p buffers
+  V* z[2];
+  V* q[2];
+  double* part[2];  // [tile][4] product partials, alternating with the buffers
+  double* part3;    // [tile][4] residual partials
   SysState* ss;
 };
 
@@ -103,12 +106,12 @@ __device__ __forceinline__ void tile_partial(double (&v)[NV], double* part) {
   block_partial<NV>(v, part);
 }
 
-__global__ void k_sys_init(SysState* ss, int n_sys, int max_it, int stag_checks) {
+__global__ void k_sys_init(SysState* ss, int n_sys, int max_it, int stag_it) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n_sys) return;
   SysState z{};
   z.max_it = max_it;
-  z.stag_checks = stag_checks;
+  z.stag_it = stag_it;
   ss[s] = z;
 }
 
@@ -164,7 +167,7 @@ __global__ void __launch_bounds__(1024) k_prep(SetArgs<V, W, I> a, int x0_zero) 
     acc[1] += xi * xi;
   }
   if (err) atomicExch(&a.ss[s].err, err);
-  tile_partial<2>(acc, a.part4 + 4 * (size_t)t);
+  tile_partial<2>(acc, a.part[0] + 4 * (size_t)t);
 }
 
 // One block per system: ||b||, the tolerance, the input checks.
@@ -172,7 +175,7 @@ template <typename V, typename W, typename I>
 __global__ void k_sys_start(SetArgs<V, W, I> a, double tol) {
   const int s = blockIdx.x;
   double r[2];
-  sum_range<2>(a.part4, a.sys_tile0[s], a.sys_tile0[s + 1], r);
+  sum_range<2>(a.part[0], a.sys_tile0[s], a.sys_tile0[s + 1], r);
   if (threadIdx.x != 0) return;
   SysState& S = a.ss[s];
   S.bnorm2 = r[0];
@@ -193,8 +196,8 @@ __global__ void k_sys_start(SetArgs<V, W, I> a, double tol) {
 // True residuals from the float64 CSR with error-free transformations, for the
 // returned vector x_hi (stopping test) and for x_hi + x_lo (replacement);
 // tile partials of ||r_hi||^2, z.D'z and || |A||x_hi| ||^2 (rounding floor).
-//   mode 0 (start):   z = r_dd/d', p = z
-//   mode 1 (replace): z = r_dd/d'
+//   mode 0 (start):   z = r_dd/d', p = z   (buffer 0)
+//   mode 1 (replace): z = r_dd/d'          (buffer 0)
 //   mode 2 (final):   norms only, also for stopped systems
 template <typename V, typename W, typename I>
 __global__ void __launch_bounds__(1024) k_resid(SetArgs<V, W, I> a, int mode) {
@@ -210,8 +213,8 @@ __global__ void __launch_bounds__(1024) k_resid(SetArgs<V, W, I> a, int mode) {
     if (mode != 2) {
       const double d = a.dp[i];
       const V zv = (V)(rd / d);
-      a.z[i] = zv;
-      if (mode == 0) a.p[i] = zv;
+      a.z[0][i] = zv;
+      if (mode == 0) a.p[0][i] = zv;
       const double zd = (double)zv;
       acc[1] += d * zd * zd;
     }
@@ -220,9 +223,9 @@ __global__ void __launch_bounds__(1024) k_resid(SetArgs<V, W, I> a, int mode) {
 }
 
 // One block per system after k_resid: the convergence test on the returned
-// vector; the stagnation test (the residual norm has not halved for
-// stag_checks replacement points although it is within 1000x of the tolerance
-// or of the rounding floor u*|| |A||x| ||); the scalars of the next direction.
+// vector; the stagnation test (the best residual norm is within 100x of the
+// rounding floor u || |A||x| || and has not halved for max(stag_it, k_best)
+// iterations); the scalars of the next direction.
 template <typename V, typename W, typename I>
 __global__ void k_sys_check(SetArgs<V, W, I> a, int mode) {
   const int s = blockIdx.x;
@@ -243,56 +246,70 @@ __global__ void k_sys_check(SetArgs<V, W, I> a, int mode) {
   } else if (mode == 0) {
     S.rho = r[1];
     S.best_res2 = r[0];
-    S.stall = 0;
+    S.k_best = S.iter;
   } else {
     if (r[0] < 0.25 * S.best_res2) {
       S.best_res2 = r[0];
-      S.stall = 0;
-    } else {
-      S.stall += 1;
+      S.k_best = S.iter;
     }
     const double floor2 = 0x1p-106 * r[2];
-    if (S.best_res2 < 1e6 * fmax(S.tol2, floor2) && S.stall >= S.stag_checks) {
+    const int window = S.stag_it > S.k_best ? S.stag_it : S.k_best;
+    if (S.best_res2 < 1e4 * floor2 && S.iter - S.k_best >= window) {
       S.status = PM_STAGNATED;
       S.done = 1;
     } else {
       S.beta = r[1] / S.rho;
       S.rho = r[1];
+      S.iter_base = S.iter;
     }
   }
 }
 
-// p = z + beta p after a replacement.
+// p = z + beta p after a replacement: z in buffer 0, the old p in buffer
+// `src`, the new p in buffer 0.
 template <typename V, typename W, typename I>
-__global__ void __launch_bounds__(1024) k_pdir(SetArgs<V, W, I> a) {
+__global__ void __launch_bounds__(1024) k_pdir(SetArgs<V, W, I> a, int src) {
   const int t = xcd_block(blockIdx.x, gridDim.x);
   const SysState& S = a.ss[a.tile_sys[t]];
   if (S.done) return;
   const double be = S.beta;
+  const V* ps = a.p[src];
+  V* pd = a.p[0];
   for (int i = a.tile_r0[t] + threadIdx.x; i < a.tile_r1[t]; i += blockDim.x)
-    a.p[i] = (V)((double)a.z[i] + be * (double)a.p[i]);
+    pd[i] = (V)((double)a.z[0][i] + be * (double)ps[i]);
 }
 
 // Rows handled per thread and loop trip: every load of the group is issued
 // before the first use, so each thread keeps R rows of memory traffic in flight.
 constexpr int kUnroll = 4;
+constexpr int kUnrollIter = 2;
 
-// q~ = D'^{-1} A p (difference form) and, with q = D' q~ as stored, the tile
+// Stop decision of an update from the reduced product partials (identical in
+// every block of the system): 0 = go on, 100 = exact zero residual, else the
+// status.
+__device__ __forceinline__ int stop_code(int k, int max_it, double pq, double rho) {
+  if (k > max_it) return PM_MAXIT;
+  if (rho == 0.0) return 100;
+  if (!(pq > 0.0) || !isfinite(pq) || !isfinite(rho)) return PM_BREAKDOWN;
+  return 0;
+}
+
+// Plain product on buffer 0 (the first iteration of a chunk):
+// q~ = D'^{-1} A p in difference form and, with q = D' q~ as stored, the tile
 // partials of  s0 = p.q,  s1 = z.q (= q.D'^{-1} r),  s2 = q.D'^{-1} q,
-// s3 = z.D' z (= rho).
+// s3 = z.D' z (= rho), into part[0].
 template <typename V, typename W, typename I>
 __global__ void __launch_bounds__(1024) k_spmv(SetArgs<V, W, I> a) {
   const int t = xcd_block(blockIdx.x, gridDim.x);
   const int s = a.tile_sys[t];
-  SysState& S = a.ss[s];
-  if (S.done) return;
+  if (a.ss[s].done) return;
   const int N = a.N;
   const W* __restrict__ c = a.c;
   const W* __restrict__ w = a.w;
   const I* __restrict__ idx = a.idx;
-  const V* __restrict__ p = a.p;
-  const V* __restrict__ z = a.z;
-  V* __restrict__ q = a.q;
+  const V* __restrict__ p = a.p[0];
+  const V* __restrict__ z = a.z[0];
+  V* __restrict__ q = a.q[0];
   const int r0 = a.tile_r0[t], r1 = a.tile_r1[t];
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int base = r0 + threadIdx.x; base < r1; base += kUnroll * blockDim.x) {
@@ -343,35 +360,207 @@ __global__ void __launch_bounds__(1024) k_spmv(SetArgs<V, W, I> a) {
       acc[3] += d * zi * zi;
     }
   }
-  tile_partial<4>(acc, a.part4 + 4 * (size_t)t);
-  if (t == a.sys_tile0[s] && threadIdx.x == 0) S.iter_pending = S.iter + 1;
+  tile_partial<4>(acc, a.part[0] + 4 * (size_t)t);
 }
 
-// Every block reduces its system's product partials (same order, same
-// result): alpha = rho / p.q, the next rho by its recurrence anchored on the
-// exact rho, beta = rho_next / rho; then
-//   FLUSH = false:  x_acc += alpha p;  z -= alpha q~;  p = z + beta p
-//   FLUSH = true :  (x_hi, x_lo) += x_acc + alpha p; x_acc = 0 (replacement
-//                   iteration: z and p are rebuilt from the true residual)
-// The system's first tile records the scalars and the iteration count, or
-// the stop status.  `scale` multiplies alpha and beta (1 in solves, 0 when the
+// Partials of a system's tiles, loaded by the threads of a block before they
+// are needed: thread tid holds tiles t0 + tid + u * blockDim (u < kPartU) as
+// two 16-byte loads each; partial_reduce() adds them in a fixed order (then
+// any further tiles, then across lanes and waves), so every block of the
+// system obtains the same sums.
+constexpr int kPartU = 4;
+
+struct PartRegs {
+  double2 v[kPartU][2];
+};
+
+// Branch-free: every thread loads a valid tile (its own, or the system's last
+// one) and partial_reduce() drops the copies, so no load waits on another.
+__device__ __forceinline__ void partial_load(const double* __restrict__ part, int t0, int t1,
+                                             PartRegs& P) {
+  const double2* p2 = reinterpret_cast<const double2*>(part);
+#pragma unroll
+  for (int u = 0; u < kPartU; ++u) {
+    const int tt = t0 + (int)threadIdx.x + u * (int)blockDim.x;
+    const size_t tc = (size_t)(tt < t1 ? tt : t1 - 1);
+    P.v[u][0] = p2[2 * tc];
+    P.v[u][1] = p2[2 * tc + 1];
+  }
+}
+
+__device__ __forceinline__ void partial_reduce(const double* __restrict__ part, int t0, int t1,
+                                               const PartRegs& P, double (&out)[4]) {
+  __shared__ double sh[4][16];
+  __shared__ double res[4];
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int u = 0; u < kPartU; ++u) {
+    const bool own = t0 + (int)threadIdx.x + u * (int)blockDim.x < t1;
+    v[0] += own ? P.v[u][0].x : 0.0;
+    v[1] += own ? P.v[u][0].y : 0.0;
+    v[2] += own ? P.v[u][1].x : 0.0;
+    v[3] += own ? P.v[u][1].y : 0.0;
+  }
+  for (int tt = t0 + (int)threadIdx.x + kPartU * (int)blockDim.x; tt < t1; tt += blockDim.x)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] += part[4 * (size_t)tt + k];
+  wave_sum<4>(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) sh[k][wid] = v[k];
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    double acc = 0.0;
+    for (int w = 0; w < nw; ++w) acc += sh[threadIdx.x][w];
+    res[threadIdx.x] = acc;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 4; ++k) out[k] = res[k];
+}
+
+// The rows one thread handles in one trip of the fused iteration, with their
+// neighbours' p, z and q~.
+template <typename V, typename W, typename I, int R>
+struct Trip {
+  int row[R];
+  W w0[R], w1[R], w2[R], cc[R];
+  I i0[R], i1[R], i2[R];
+  V pv[R], zv[R], qv[R], xv[R];
+  V gp[3][R], gz[3][R], gq[3][R];
+};
+
+template <typename V, typename W, typename I, int R>
+__device__ __forceinline__ void trip_direct(Trip<V, W, I, R>& T, const SetArgs<V, W, I>& a,
+                                            const V* __restrict__ ps, const V* __restrict__ zs,
+                                            const V* __restrict__ qs, int base, int r0, int r1) {
+  const size_t N = (size_t)a.N;
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const int i0r = base + u * (int)blockDim.x;
+    T.row[u] = i0r < r1 ? i0r : -1;
+    const int i = i0r < r1 ? i0r : r0;  // a valid row keeps the loads in bounds
+    T.w0[u] = a.w[i];
+    T.w1[u] = a.w[N + i];
+    T.w2[u] = a.w[2 * N + i];
+    T.i0[u] = a.idx[i];
+    T.i1[u] = a.idx[N + i];
+    T.i2[u] = a.idx[2 * N + i];
+    T.cc[u] = a.c[i];
+    T.pv[u] = ps[i];
+    T.zv[u] = zs[i];
+    T.qv[u] = qs[i];
+    T.xv[u] = a.xacc[i];
+  }
+}
+
+template <typename V, typename W, typename I, int R>
+__device__ __forceinline__ void trip_gather(Trip<V, W, I, R>& T, const V* __restrict__ ps,
+                                            const V* __restrict__ zs, const V* __restrict__ qs,
+                                            int r0) {
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const int i = T.row[u] >= 0 ? T.row[u] : r0;
+    const int j0 = col_of<I>(i, T.i0[u]), j1 = col_of<I>(i, T.i1[u]), j2 = col_of<I>(i, T.i2[u]);
+    T.gp[0][u] = ps[j0];
+    T.gz[0][u] = zs[j0];
+    T.gq[0][u] = qs[j0];
+    T.gp[1][u] = ps[j1];
+    T.gz[1][u] = zs[j1];
+    T.gq[1][u] = qs[j1];
+    T.gp[2][u] = ps[j2];
+    T.gz[2][u] = zs[j2];
+    T.gq[2][u] = qs[j2];
+  }
+}
+
+// The update and product for the rows of one trip (see k_iter).
+template <typename V, typename W, typename I, int R>
+__device__ __forceinline__ void trip_compute(const Trip<V, W, I, R>& T, double as, double bs,
+                                             V* __restrict__ pd, V* __restrict__ zd,
+                                             V* __restrict__ qd, V* __restrict__ xacc,
+                                             double (&acc)[4]) {
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    if (T.row[u] < 0) continue;
+    const int i = T.row[u];
+    const double pold = (double)T.pv[u];
+    xacc[i] = (V)((double)T.xv[u] + as * pold);
+    const V zn = (V)((double)T.zv[u] - as * (double)T.qv[u]);
+    const V pn = (V)((double)zn + bs * pold);
+    zd[i] = zn;
+    pd[i] = pn;
+    double g[3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      const V zj = (V)((double)T.gz[e][u] - as * (double)T.gq[e][u]);
+      g[e] = (double)(V)((double)zj + bs * (double)T.gp[e][u]);
+    }
+    const double pi = (double)pn;
+    const double ci = (double)T.cc[u];
+    double y = ci * pi;
+    y += (double)T.w0[u] * (pi - g[0]);
+    y += (double)T.w1[u] * (pi - g[1]);
+    y += (double)T.w2[u] * (pi - g[2]);
+    const double d = ((ci + (double)T.w0[u]) + (double)T.w1[u]) + (double)T.w2[u];
+    const V qn = (V)(y / d);
+    qd[i] = qn;
+    const double qq = (double)qn, zi = (double)zn;
+    const double dq = d * qq;
+    acc[0] += pi * dq;
+    acc[1] += zi * dq;
+    acc[2] += qq * dq;
+    acc[3] += d * zi * zi;
+  }
+}
+
+// Iteration k = iter_base + j of a chunk (1 <= j < m), reading buffer src and
+// writing buffer dst = src ^ 1.  Every block reduces its system's partials of
+// the last product (same order, same result): alpha = rho / p.q, the next rho
+// by its recurrence anchored on the exact rho, beta = rho_next / rho.  Then,
+// for the rows of the tile,
+//   x_acc += alpha p;  z' = z - alpha q~;  p' = z' + beta p
+// and at once q~' = D'^{-1} A p' with the tile partials of the next product.
+// The p' of a neighbour row comes from that row's p, z and q~ in buffer src by
+// the same expression (same roundings) its own block evaluates, so every block
+// sees the same p'.  Loads are software-pipelined: the first trip's rows and
+// the partials are all in flight before the reduction waits on any of them,
+// and each later trip's rows are loaded while the trip before is computed, so
+// a trip costs one memory round trip (the neighbour gathers), not two.  The
+// system's first tile records the scalars and the iteration count, or the
+// stop status.  `scale` multiplies alpha and beta (1 in solves, 0 when the
 // kernel is timed).
-template <typename V, typename W, typename I, bool FLUSH>
-__global__ void __launch_bounds__(1024) k_update(SetArgs<V, W, I> a, double scale) {
+template <typename V, typename W, typename I, int R>
+__global__ void __launch_bounds__(512) k_iter(SetArgs<V, W, I> a, int src, int j, double scale) {
   const int t = xcd_block(blockIdx.x, gridDim.x);
   const int s = a.tile_sys[t];
   SysState& S = a.ss[s];
   if (S.done) return;
+  const int r0 = a.tile_r0[t], r1 = a.tile_r1[t];
+  const int t0 = a.sys_tile0[s], t1 = a.sys_tile0[s + 1];
+  const V* __restrict__ ps = a.p[src];
+  const V* __restrict__ zs = a.z[src];
+  const V* __restrict__ qs = a.q[src];
+  V* __restrict__ pd = a.p[src ^ 1];
+  V* __restrict__ zd = a.z[src ^ 1];
+  V* __restrict__ qd = a.q[src ^ 1];
+  V* __restrict__ xacc = a.xacc;
+  const int step = R * (int)blockDim.x;
+  int base = r0 + (int)threadIdx.x;
+
+  Trip<V, W, I, R> Ta, Tb;
+  trip_direct<V, W, I, R>(Ta, a, ps, zs, qs, base, r0, r1);
+  PartRegs P;
+  partial_load(a.part[src], t0, t1, P);
+  trip_gather<V, W, I, R>(Ta, ps, zs, qs, r0);
   double r[4];
-  sum_range<4>(a.part4, a.sys_tile0[s], a.sys_tile0[s + 1], r);
-  const bool first = t == a.sys_tile0[s] && threadIdx.x == 0;
-  const int k = S.iter_pending;
+  partial_reduce(a.part[src], t0, t1, P, r);
+
+  const bool first = t == t0 && threadIdx.x == 0;
+  const int k = S.iter_base + j;
   const double pq = r[0], rho = r[3];
-  int stop = 0;
-  if (k > S.max_it) stop = PM_MAXIT;
-  else if (rho == 0.0) stop = 100;  // exact zero residual in the recurrence
-  else if (!(pq > 0.0) || !isfinite(pq) || !isfinite(rho)) stop = PM_BREAKDOWN;
-  if (stop) {
+  if (const int stop = stop_code(k, S.max_it, pq, rho)) {
     if (first) {
       S.status = stop == 100 ? PM_OK : stop;
       S.done = 1;
@@ -382,49 +571,147 @@ __global__ void __launch_bounds__(1024) k_update(SetArgs<V, W, I> a, double scal
   const double rn = rho - 2.0 * al * r[1] + al * al * r[2];
   const double be = rn / rho;
   const double as = al * scale, bs = be * scale;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  // two trip buffers in turn; loads past the tile end are clamped to row r0
+  // and flagged, so they are always in bounds
+  for (;;) {
+    base += step;
+    bool more = base < r1;
+    trip_direct<V, W, I, R>(Tb, a, ps, zs, qs, base, r0, r1);
+    trip_compute<V, W, I, R>(Ta, as, bs, pd, zd, qd, xacc, acc);
+    if (!more) break;
+    trip_gather<V, W, I, R>(Tb, ps, zs, qs, r0);
+    base += step;
+    more = base < r1;
+    trip_direct<V, W, I, R>(Ta, a, ps, zs, qs, base, r0, r1);
+    trip_compute<V, W, I, R>(Tb, as, bs, pd, zd, qd, xacc, acc);
+    if (!more) break;
+    trip_gather<V, W, I, R>(Ta, ps, zs, qs, r0);
+  }
+  tile_partial<4>(acc, a.part[src ^ 1] + 4 * (size_t)t);
+  if (first) {
+    S.alpha = al;
+    S.beta = be;
+    S.rho = rho;
+    S.iter = k;
+  }
+}
+
+// Split schedule (the tuner may prefer it where the fused kernel's extra
+// neighbour gathers cost more than the pass it saves): after k_spmv on buffer
+// 0, iteration k = iter_base + j updates x_acc, z and p in place with the
+// scalars from part[0].
+template <typename V, typename W, typename I>
+__global__ void __launch_bounds__(1024) k_update(SetArgs<V, W, I> a, int j, double scale) {
+  const int t = xcd_block(blockIdx.x, gridDim.x);
+  const int s = a.tile_sys[t];
+  SysState& S = a.ss[s];
+  if (S.done) return;
+  const int r0 = a.tile_r0[t], r1 = a.tile_r1[t];
+  const int t0 = a.sys_tile0[s], t1 = a.sys_tile0[s + 1];
+  V* __restrict__ p = a.p[0];
+  V* __restrict__ z = a.z[0];
+  const V* __restrict__ q = a.q[0];
+  V* __restrict__ xacc = a.xacc;
+  int base = r0 + (int)threadIdx.x;
+  V xa[kUnroll], pp[kUnroll], zz[kUnroll], qq[kUnroll];
+  auto load = [&](int b0) {
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int i = b0 + u * (int)blockDim.x;
+      const int jj = i < r1 ? i : r0;
+      xa[u] = xacc[jj];
+      pp[u] = p[jj];
+      zz[u] = z[jj];
+      qq[u] = q[jj];
+    }
+  };
+  load(base);
+  PartRegs P;
+  partial_load(a.part[0], t0, t1, P);
+  double r[4];
+  partial_reduce(a.part[0], t0, t1, P, r);
+  const bool first = t == t0 && threadIdx.x == 0;
+  const int k = S.iter_base + j;
+  const double pq = r[0], rho = r[3];
+  if (const int stop = stop_code(k, S.max_it, pq, rho)) {
+    if (first) {
+      S.status = stop == 100 ? PM_OK : stop;
+      S.done = 1;
+    }
+    return;
+  }
+  const double al = rho / pq;
+  const double rn = rho - 2.0 * al * r[1] + al * al * r[2];
+  const double be = rn / rho;
+  const double as = al * scale, bs = be * scale;
+  while (base < r1) {
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int i = base + u * (int)blockDim.x;
+      if (i >= r1) continue;
+      const double pi = (double)pp[u];
+      xacc[i] = (V)((double)xa[u] + as * pi);
+      const V zv = (V)((double)zz[u] - as * (double)qq[u]);
+      z[i] = zv;
+      p[i] = (V)((double)zv + bs * pi);
+    }
+    base += kUnroll * (int)blockDim.x;
+    if (base < r1) load(base);
+  }
+  if (first) {
+    S.alpha = al;
+    S.beta = be;
+    S.rho = rho;
+    S.iter = k;
+  }
+}
+
+// Last iteration of a chunk (k = iter_base + m): the same scalars from the
+// partials in part[src], then (x_hi, x_lo) += x_acc + alpha p and x_acc = 0;
+// z and p are rebuilt from the true residual afterwards.
+template <typename V, typename W, typename I>
+__global__ void __launch_bounds__(1024) k_update_flush(SetArgs<V, W, I> a, int src, int j) {
+  const int t = xcd_block(blockIdx.x, gridDim.x);
+  const int s = a.tile_sys[t];
+  SysState& S = a.ss[s];
+  if (S.done) return;
+  double r[4];
+  sum_range<4>(a.part[src], a.sys_tile0[s], a.sys_tile0[s + 1], r);
+  const bool first = t == a.sys_tile0[s] && threadIdx.x == 0;
+  const int k = S.iter_base + j;
+  const double pq = r[0], rho = r[3];
+  if (const int stop = stop_code(k, S.max_it, pq, rho)) {
+    if (first) {
+      S.status = stop == 100 ? PM_OK : stop;
+      S.done = 1;
+    }
+    return;
+  }
+  const double al = rho / pq;
+  const double rn = rho - 2.0 * al * r[1] + al * al * r[2];
+  const double be = rn / rho;
+  const V* __restrict__ ps = a.p[src];
   const int r0 = a.tile_r0[t], r1 = a.tile_r1[t];
   for (int base = r0 + threadIdx.x; base < r1; base += kUnroll * blockDim.x) {
-    if (FLUSH) {
-      double xa[kUnroll], pp[kUnroll], hi[kUnroll], lo[kUnroll];
+    double xa[kUnroll], pp[kUnroll], hi[kUnroll], lo[kUnroll];
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const int i = base + u * (int)blockDim.x;
-        const int j = i < r1 ? i : r0;
-        xa[u] = (double)a.xacc[j];
-        pp[u] = (double)a.p[j];
-        hi[u] = a.x64[j];
-        lo[u] = a.xlo[j];
-      }
+    for (int u = 0; u < kUnroll; ++u) {
+      const int i = base + u * (int)blockDim.x;
+      const int jj = i < r1 ? i : r0;
+      xa[u] = (double)a.xacc[jj];
+      pp[u] = (double)ps[jj];
+      hi[u] = a.x64[jj];
+      lo[u] = a.xlo[jj];
+    }
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const int i = base + u * (int)blockDim.x;
-        if (i >= r1) continue;
-        dd_add(hi[u], lo[u], xa[u] + as * pp[u]);
-        a.x64[i] = hi[u];
-        a.xlo[i] = lo[u];
-        a.xacc[i] = V(0);
-      }
-    } else {
-      V xa[kUnroll], pp[kUnroll], zz[kUnroll], qq[kUnroll];
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const int i = base + u * (int)blockDim.x;
-        const int j = i < r1 ? i : r0;
-        xa[u] = a.xacc[j];
-        pp[u] = a.p[j];
-        zz[u] = a.z[j];
-        qq[u] = a.q[j];
-      }
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const int i = base + u * (int)blockDim.x;
-        if (i >= r1) continue;
-        const double pi = (double)pp[u];
-        a.xacc[i] = (V)((double)xa[u] + as * pi);
-        const V zv = (V)((double)zz[u] - as * (double)qq[u]);
-        a.z[i] = zv;
-        a.p[i] = (V)((double)zv + bs * pi);
-      }
+    for (int u = 0; u < kUnroll; ++u) {
+      const int i = base + u * (int)blockDim.x;
+      if (i >= r1) continue;
+      dd_add(hi[u], lo[u], xa[u] + al * pp[u]);
+      a.x64[i] = hi[u];
+      a.xlo[i] = lo[u];
+      a.xacc[i] = V(0);
     }
   }
   if (first) {
@@ -464,7 +751,7 @@ __global__ void k_timing_state(SysState* ss, int n_sys) {
   ss[s].status = PM_OK;
   ss[s].max_it = INT_MAX;
   ss[s].iter = 0;
-  ss[s].iter_pending = 1;
+  ss[s].iter_base = 0;
   ss[s].tol2 = -1.0;
 }
 
@@ -546,100 +833,128 @@ SetArgs<V, W, I> make_args(SolveSet& S, const double* val, const double* b, doub
   a.xlo = S.xlo;
   a.b64 = S.b64;
   a.xacc = (V*)S.xacc;
-  a.p = (V*)S.p;
-  a.z = (V*)S.z;
-  a.q = (V*)S.q;
-  a.part4 = S.part4;
+  for (int k = 0; k < 2; ++k) {
+    a.p[k] = (V*)S.p[k];
+    a.z[k] = (V*)S.z[k];
+    a.q[k] = (V*)S.q[k];
+    a.part[k] = S.part[k];
+  }
   a.part3 = S.part3;
   a.ss = S.ss;
   return a;
 }
 
+// Launch shape: rows per tile, threads per block, rows per thread and trip of
+// the fused iteration kernel (0: split schedule, k_update then k_spmv).
+struct Launch {
+  int tile, block, rows;
+};
+
 template <typename V, typename W, typename I>
 struct Ops {
   using A = SetArgs<V, W, I>;
-  static void start(SolveSet& S, const A& a, const pm_opts& o, int block, hipStream_t s) {
-    const int G = S.n_tiles;
+  static void start(SolveSet& S, const A& a, const pm_opts& o, const Launch& L, hipStream_t s) {
+    const int checks = o.stag_checks > 0 ? o.stag_checks : 40;
+    const long win = (long)checks * o.replace_every;
     k_sys_init<<<(S.n_sys + 63) / 64, 64, 0, s>>>(S.ss, S.n_sys, o.max_it,
-                                                  o.stag_checks > 0 ? o.stag_checks : 40);
-    k_prep<V, W, I><<<G, block, 0, s>>>(a, o.x0_is_zero);
+                                                  (int)std::min<long>(win, INT_MAX));
+    k_prep<V, W, I><<<S.n_tiles, L.block, 0, s>>>(a, o.x0_is_zero);
     k_sys_start<V, W, I><<<S.n_sys, 256, 0, s>>>(a, o.tol);
-    resid(S, a, 0, block, s);
+    resid(S, a, 0, L, s);
   }
-  static void resid(SolveSet& S, const A& a, int mode, int block, hipStream_t s) {
-    k_resid<V, W, I><<<S.n_tiles, block, 0, s>>>(a, mode);
+  static void resid(SolveSet& S, const A& a, int mode, const Launch& L, hipStream_t s) {
+    k_resid<V, W, I><<<S.n_tiles, L.block, 0, s>>>(a, mode);
     k_sys_check<V, W, I><<<S.n_sys, 256, 0, s>>>(a, mode);
   }
-  static void spmv(SolveSet& S, const A& a, int block, hipStream_t s) {
-    k_spmv<V, W, I><<<S.n_tiles, block, 0, s>>>(a);
+  static void spmv(SolveSet& S, const A& a, const Launch& L, hipStream_t s) {
+    k_spmv<V, W, I><<<S.n_tiles, L.block, 0, s>>>(a);
   }
-  static void update(SolveSet& S, const A& a, int block, hipStream_t s, double scale) {
-    k_update<V, W, I, false><<<S.n_tiles, block, 0, s>>>(a, scale);
-  }
-  static void chunk(SolveSet& S, const A& a, int mrep, int block, hipStream_t s) {
-    for (int it = 0; it < mrep - 1; ++it) {
-      spmv(S, a, block, s);
-      update(S, a, block, s, 1.0);
+  // One iteration after the product of the last: the fused kernel (buffers
+  // src -> src ^ 1), or the split schedule's update then product (buffer 0).
+  static void iter(SolveSet& S, const A& a, int src, int j, const Launch& L, hipStream_t s,
+                   double scale) {
+    if (L.rows == 0) {
+      k_update<V, W, I><<<S.n_tiles, L.block, 0, s>>>(a, j, scale);
+      spmv(S, a, L, s);
+    } else if (L.rows == 1) {
+      k_iter<V, W, I, 1><<<S.n_tiles, L.block, 0, s>>>(a, src, j, scale);
+    } else if (L.rows == 4 && sizeof(V) == 4) {  // float64 at 4 rows would spill
+      if constexpr (sizeof(V) == 4) k_iter<V, W, I, 4><<<S.n_tiles, L.block, 0, s>>>(a, src, j, scale);
+    } else {
+      k_iter<V, W, I, 2><<<S.n_tiles, L.block, 0, s>>>(a, src, j, scale);
     }
-    spmv(S, a, block, s);
-    k_update<V, W, I, true><<<S.n_tiles, block, 0, s>>>(a, 1.0);
-    resid(S, a, 1, block, s);
-    k_pdir<V, W, I><<<S.n_tiles, block, 0, s>>>(a);
   }
-  static void finish(SolveSet& S, const A& a, int block, hipStream_t s) {
-    k_flush<V, W, I><<<S.n_tiles, block, 0, s>>>(a);
-    resid(S, a, 2, block, s);
-    k_scatter<V, W, I><<<S.n_tiles, block, 0, s>>>(a);
+  // m iterations: product on buffer 0, m - 1 iterations (fused: alternating
+  // the buffers), the flushing m-th update, the replacement and the new
+  // direction (back in buffer 0).
+  static void chunk(SolveSet& S, const A& a, int m, const Launch& L, hipStream_t s) {
+    spmv(S, a, L, s);
+    int src = 0;
+    for (int j = 1; j < m; ++j) {
+      iter(S, a, src, j, L, s, 1.0);
+      if (L.rows != 0) src ^= 1;
+    }
+    k_update_flush<V, W, I><<<S.n_tiles, L.block, 0, s>>>(a, src, m);
+    resid(S, a, 1, L, s);
+    k_pdir<V, W, I><<<S.n_tiles, L.block, 0, s>>>(a, src);
+  }
+  static void finish(SolveSet& S, const A& a, const Launch& L, hipStream_t s) {
+    k_flush<V, W, I><<<S.n_tiles, L.block, 0, s>>>(a);
+    resid(S, a, 2, L, s);
+    k_scatter<V, W, I><<<S.n_tiles, L.block, 0, s>>>(a);
   }
 };
 
-// Tile sizes tried by the tuner; the choice is cached per shape.
-constexpr int kTileCandidates[] = {1024, 2048, 4096, 8192};
+// Launch shapes tried by the tuner (timing the fused iteration kernel on the
+// real matrix); the choice is cached per problem shape and precision.
+constexpr Launch kCandidates[] = {
+    {512, 256, 1},  {1024, 256, 1}, {1024, 256, 2}, {2048, 256, 2}, {2048, 256, 4},
+    {4096, 256, 4}, {2048, 512, 1}, {2048, 512, 2}, {4096, 512, 2}, {4096, 512, 4},
+    {8192, 512, 4}, {1024, 256, 0}, {2048, 256, 0}, {4096, 256, 0}, {4096, 512, 0},
+};
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int, int>, int> g_tuned;
+std::map<std::tuple<int, int, int, int>, Launch> g_tuned;
 
 template <typename V, typename W, typename I>
-int tune_tile(SolveSet& S, const double* val64, const double* b, double* x, const pm_opts& o,
-              int block, hipStream_t s, int* best_tile) {
+int tune_launch(SolveSet& S, const double* val64, const double* b, double* x, const pm_opts& o,
+                hipStream_t s, Launch* best_launch) {
   const auto key = std::make_tuple(S.N, S.n_sys, o.precision, S.index_bits);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tuned.find(key);
     if (it != g_tuned.end()) {
-      *best_tile = it->second;
+      *best_launch = it->second;
       return PM_OK;
     }
   }
   double best = 1e300;
-  int arg = 2048;
+  Launch arg = {2048, 256, 2};
   pm_opts ot = o;
   ot.max_it = INT_MAX;
-  for (int tile : kTileCandidates) {
-    if (int r = build_tiles(S, tile)) return r;
+  for (const Launch& L : kCandidates) {
+    if ((long)L.tile * 2 > (long)S.N && L.tile != kCandidates[0].tile) continue;
+    if (L.rows == 4 && sizeof(V) == 8) continue;
+    if (int r = build_tiles(S, L.tile)) return r;
     const auto a = make_args<V, W, I>(S, val64, b, x);
-    Ops<V, W, I>::start(S, a, ot, block, s);
-    for (int w = 0; w < 3; ++w) {  // warm caches and clocks
-      Ops<V, W, I>::spmv(S, a, block, s);
-      Ops<V, W, I>::update(S, a, block, s, 0.0);
-    }
+    Ops<V, W, I>::start(S, a, ot, L, s);
+    Ops<V, W, I>::spmv(S, a, L, s);
+    for (int w = 0; w < 4; ++w)  // warm caches and clocks
+      Ops<V, W, I>::iter(S, a, w & 1, 1, L, s, 0.0);
     PS_HIP(hipEventRecord(S.tev[0], s));
     const int reps = 20;
-    for (int w = 0; w < reps; ++w) {
-      Ops<V, W, I>::spmv(S, a, block, s);
-      Ops<V, W, I>::update(S, a, block, s, 0.0);
-    }
+    for (int w = 0; w < reps; ++w) Ops<V, W, I>::iter(S, a, w & 1, 1, L, s, 0.0);
     PS_HIP(hipEventRecord(S.tev[1], s));
     PS_HIP(hipEventSynchronize(S.tev[1]));
     float ms = 0.f;
     PS_HIP(hipEventElapsedTime(&ms, S.tev[0], S.tev[1]));
     if (ms < best) {
       best = ms;
-      arg = tile;
+      arg = L;
     }
   }
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tuned[key] = arg;
-  *best_tile = arg;
+  *best_launch = arg;
   return PM_OK;
 }
 
@@ -647,37 +962,42 @@ template <typename V, typename W, typename I>
 int run(SolveSet& S, const double* val64, const double* b, double* x, const pm_opts& o,
         pm_info* infos, hipStream_t s) {
   using O = Ops<V, W, I>;
-  const int block = o.block > 0 ? std::min(1024, std::max(64, (o.block / 64) * 64)) : 256;
-  int tile = o.tile_rows > 0 ? std::max(kMinTile, o.tile_rows) : 0;
-  if (tile == 0) {
-    if (int r = tune_tile<V, W, I>(S, val64, b, x, o, block, s, &tile)) return r;
+  Launch L;
+  if (o.tile_rows > 0) {
+    const int block = o.block > 0 ? std::min(512, std::max(64, (o.block / 64) * 64)) : 256;
+    L = {std::max(kMinTile, o.tile_rows), block,
+         o.iter_rows == -1 ? 0 : (o.iter_rows == 0 ? 1 : o.iter_rows)};
+  } else {
+    if (int r = tune_launch<V, W, I>(S, val64, b, x, o, s, &L)) return r;
   }
-  if (int r = build_tiles(S, tile)) return r;
+  if (int r = build_tiles(S, L.tile)) return r;
   const auto a = make_args<V, W, I>(S, val64, b, x);
   S.last_prec = o.precision;
-  S.last_tile = tile;
-  S.last_block = block;
+  S.last_tile = L.tile;
+  S.last_block = L.block;
+  S.last_rows = L.rows;
   S.last_val = val64;
 
-  O::start(S, a, o, block, s);
+  O::start(S, a, o, L, s);
   PS_HIP(hipGetLastError());
 
-  if (!S.graph || S.g_prec != o.precision || S.g_m != o.replace_every || S.g_tile != tile ||
-      S.g_block != block || S.g_val != val64) {
+  if (!S.graph || S.g_prec != o.precision || S.g_m != o.replace_every || S.g_tile != L.tile ||
+      S.g_block != L.block || S.g_rows != L.rows || S.g_val != val64) {
     if (S.graph) {
       (void)hipGraphExecDestroy(S.graph);
       S.graph = nullptr;
     }
     hipGraph_t g = nullptr;
     PS_HIP(hipStreamBeginCapture(S.cap, hipStreamCaptureModeThreadLocal));
-    O::chunk(S, a, o.replace_every, block, S.cap);
+    O::chunk(S, a, o.replace_every, L, S.cap);
     PS_HIP(hipStreamEndCapture(S.cap, &g));
     PS_HIP(hipGraphInstantiate(&S.graph, g, nullptr, nullptr, 0));
     (void)hipGraphDestroy(g);
     S.g_prec = o.precision;
     S.g_m = o.replace_every;
-    S.g_tile = tile;
-    S.g_block = block;
+    S.g_tile = L.tile;
+    S.g_block = L.block;
+    S.g_rows = L.rows;
     S.g_val = val64;
   }
 
@@ -706,7 +1026,7 @@ int run(SolveSet& S, const double* val64, const double* b, double* x, const pm_o
     }
     ++c;
   }
-  O::finish(S, a, block, s);
+  O::finish(S, a, L, s);
   PS_HIP(hipGetLastError());
   SysState* fin = S.h_ss + 2 * S.n_sys;
   PS_HIP(hipMemcpyAsync(fin, S.ss, bytes, hipMemcpyDeviceToHost, s));
@@ -759,13 +1079,13 @@ int set_init(SolveSet& S, const std::vector<int>& rows, int64_t nnz, int index_b
   if ((r = salloc(S, &S.dp, N)) || (r = salloc(S, &S.x64, N)) || (r = salloc(S, &S.xlo, N)) ||
       (r = salloc(S, &S.b64, N)))
     return r;
-  void** vecs[] = {&S.xacc, &S.p, &S.z, &S.q};
+  void** vecs[] = {&S.xacc, &S.p[0], &S.p[1], &S.z[0], &S.z[1], &S.q[0], &S.q[1]};
   for (void** v : vecs) {
     if ((r = salloc(S, &d, N))) return r;
     *v = d;
   }
-  if ((r = salloc(S, &S.part4, 4 * T)) || (r = salloc(S, &S.part3, 4 * T)) ||
-      (r = salloc(S, &S.ss, (size_t)S.n_sys)))
+  if ((r = salloc(S, &S.part[0], 4 * T)) || (r = salloc(S, &S.part[1], 4 * T)) ||
+      (r = salloc(S, &S.part3, 4 * T)) || (r = salloc(S, &S.ss, (size_t)S.n_sys)))
     return r;
   PS_HIP(hipHostMalloc((void**)&S.h_ss, 3 * sizeof(SysState) * S.n_sys, hipHostMallocDefault));
   PS_HIP(hipStreamCreateWithFlags(&S.cap, hipStreamNonBlocking));
@@ -801,13 +1121,14 @@ namespace {
 template <typename V, typename W, typename I>
 int time_kernel(SolveSet& S, int which, int n_launch, hipStream_t s, double* ms) {
   const auto a = make_args<V, W, I>(S, S.last_val, nullptr, nullptr);
-  const int block = S.last_block;
+  const Launch L = {S.last_tile, S.last_block, S.last_rows};
   k_timing_state<<<(S.n_sys + 63) / 64, 64, 0, s>>>(S.ss, S.n_sys);
+  Ops<V, W, I>::spmv(S, a, L, s);  // partials for the first fused iteration
   PS_HIP(hipEventRecord(S.tev[0], s));
   for (int r = 0; r < n_launch; ++r) {
-    if (which == 0) Ops<V, W, I>::spmv(S, a, block, s);
-    else if (which == 1) Ops<V, W, I>::update(S, a, block, s, 0.0);
-    else k_resid<V, W, I><<<S.n_tiles, block, 0, s>>>(a, 2);
+    if (which == 0) Ops<V, W, I>::spmv(S, a, L, s);
+    else if (which == 1) Ops<V, W, I>::iter(S, a, r & 1, 1, L, s, 0.0);
+    else k_resid<V, W, I><<<S.n_tiles, L.block, 0, s>>>(a, 2);
   }
   PS_HIP(hipEventRecord(S.tev[1], s));
   PS_HIP(hipGetLastError());
@@ -840,7 +1161,8 @@ int set_time_kernel(SolveSet& S, int which, int n_launch, hipStream_t s, double*
   if (ms) *ms = t;
   if (bytes) {
     if (which == 0) *bytes = n * (4 * sw + 3 * si + 3 * sv);
-    else if (which == 1) *bytes = n * 7 * sv;
+    else if (which == 1 && S.last_rows == 0) *bytes = n * (4 * sw + 3 * si + 10 * sv);
+    else if (which == 1) *bytes = n * (4 * sw + 3 * si + 8 * sv);
     else *bytes = 12.0 * S.nnz + 4.0 * (n + 1) + 24.0 * n;
   }
   return PM_OK;

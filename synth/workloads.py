@@ -91,23 +91,33 @@ def channel(n_rows=276, seed=2, aniso=False):
     }
 
 
-def lognormal_batch(n_sys=64, seed=4, lo=50_000, hi=500_000):
+def _lognormal_system(args):
+    s, target, seed, mean_logk, eps0, dt = args
+    mesh = meshes.unit_square_lattice(int(target), seed * 1000 + s)
+    c = meshes.centroids(mesh)
+    prm = fields.lognormal_square(c, seed * 1000 + 500 + s, mean_logk=mean_logk, eps=eps0)
+    return {
+        "name": f"lognormal_{s}",
+        "mesh": mesh,
+        "side_tag": side_tags(mesh["group"], [meshes.G_LEFT, meshes.G_BOTTOM, meshes.G_TOP], [meshes.G_RIGHT]),
+        "params": prm,
+        "nu": NU,
+        "dt": dt,
+        "rhs": {"cp2": fields.boundary_flux_rhs(mesh, meshes.G_LEFT, -1.0)},
+        "recipe": f"unit square lattice ~{target} cells seed {seed * 1000 + s}",
+    }
+
+
+def lognormal_batch(n_sys=64, seed=4, lo=50_000, hi=500_000, workers=1):
+    """Systems are generated independently (each from its own seeds), so
+    `workers` > 1 spreads them over a process pool with identical results."""
     sizes = np.random.default_rng(seed).integers(lo, hi + 1, n_sys)
-    out = []
     eps0, mean_logk = 0.4, -6.0
     dt = math.exp(mean_logk) / (NU * eps0)
-    for s, target in enumerate(sizes.tolist()):
-        mesh = meshes.unit_square_lattice(int(target), seed * 1000 + s)
-        c = meshes.centroids(mesh)
-        prm = fields.lognormal_square(c, seed * 1000 + 500 + s, mean_logk=mean_logk, eps=eps0)
-        out.append({
-            "name": f"lognormal_{s}",
-            "mesh": mesh,
-            "side_tag": side_tags(mesh["group"], [meshes.G_LEFT, meshes.G_BOTTOM, meshes.G_TOP], [meshes.G_RIGHT]),
-            "params": prm,
-            "nu": NU,
-            "dt": dt,
-            "rhs": {"cp2": fields.boundary_flux_rhs(mesh, meshes.G_LEFT, -1.0)},
-            "recipe": f"unit square lattice ~{target} cells seed {seed * 1000 + s}",
-        })
-    return out
+    jobs = [(s, t, seed, mean_logk, eps0, dt) for s, t in enumerate(sizes.tolist())]
+    if workers > 1 and n_sys > 1:
+        import multiprocessing as mp
+
+        with mp.get_context("spawn").Pool(min(workers, n_sys)) as pool:
+            return pool.map(_lognormal_system, jobs, chunksize=1)
+    return [_lognormal_system(j) for j in jobs]

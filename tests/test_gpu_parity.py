@@ -131,6 +131,19 @@ def test_mixed_solve_reaches_fp64_accuracy(name, kind):
     assert err <= 1e-9
 
 
+@pytest.mark.parametrize("m", [1, 2, 7, 50])
+def test_replacement_period_odd_and_even(m):
+    # each chunk alternates the iteration buffers m - 1 times; odd and even m
+    # end the chunk in different buffers
+    for prec in (0, 1):
+        c, A, b, xg, info, xo, io = solve_both("chan", "cp2", prec, replace_every=m)
+        assert info["status"] == 0 and io["status"] == 0
+        assert opcg.rel_residual(A, b, xg) <= 1e-10
+        assert np.linalg.norm(xg - xo) <= 1e-9 * np.linalg.norm(xo)
+        if prec == 0:
+            assert abs(info["iters"] - io["iters"]) <= max(2 * m, 0.02 * io["iters"])
+
+
 def test_iteration_limit_and_partial_iterate():
     c, A, b, xg, info, xo, io = solve_both("c1", "cp2", 0, max_it=7)
     assert info["status"] == B().PM_MAXIT and info["iters"] == 7
@@ -159,10 +172,21 @@ def test_solves_are_deterministic_and_launch_shape_independent():
     x1, i1 = B().pcg_solve(c["mesh"], val, b)
     x2, i2 = B().pcg_solve(c["mesh"], val, b)
     assert torch.equal(x1, x2) and i1["iters"] == i2["iters"]
-    for tile in (256, 768, 4096):
-        x3, i3 = B().pcg_solve(c["mesh"], val, b, tile_rows=tile)
-        assert i3["status"] == 0
-        assert torch.linalg.norm(x3 - x1) <= 1e-9 * torch.linalg.norm(x1)
+    for prec in (0, 1):
+        xr, ir = B().pcg_solve(c["mesh"], val, b, precision=prec)
+        for tile, block, rows in ((256, 256, 1), (768, 64, 2), (4096, 512, 1), (1024, 256, -1),
+                                  (512, 128, -1), (2048, 256, 4)):
+            if rows == 4 and prec == 0:
+                continue
+            x3, i3 = B().pcg_solve(c["mesh"], val, b, precision=prec, tile_rows=tile, block=block,
+                                   iter_rows=rows)
+            assert i3["status"] == 0
+            assert torch.linalg.norm(x3 - xr) <= 1e-9 * torch.linalg.norm(xr)
+            assert B().pm_last_launch(c["mesh"]) == {"tile_rows": tile, "block": block,
+                                                      "rows": 0 if rows == -1 else rows}
+            x4, i4 = B().pcg_solve(c["mesh"], val, b, precision=prec, tile_rows=tile, block=block,
+                                   iter_rows=rows)
+            assert torch.equal(x3, x4) and i3["iters"] == i4["iters"]
 
 
 def test_error_statuses():
