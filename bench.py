@@ -184,7 +184,7 @@ def main():
     kern = {}
     if tmesh is not None:
         launch = B.pm_last_launch(tmesh)
-        fused = launch["rows"] > 0
+        fused = launch["iter_shape"] > 0
         it_name = "k_iter" if fused else "k_update+k_spmv"
         for name, which, reps in (("k_spmv", 0, 200), (it_name, 1, 200), ("k_resid", 2, 20)):
             ms, by = B.pm_time_kernel(tmesh, which, reps)

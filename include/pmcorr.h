@@ -117,10 +117,10 @@ typedef struct {
                             not halved for max(stag_checks * replace_every,
                             k_best) iterations, k_best being the iteration of
                             the last halving (default 40) */
-  int32_t iter_rows;     /* with tile_rows: rows per thread and trip of the fused
-                            iteration kernel (1, 2, or 4 in PM_MIXED; 0 = 1), or
-                            -1 for the split schedule (update kernel, then
-                            product kernel); ignored when the tuner decides */
+  int32_t iter_shape;    /* with tile_rows: the iteration schedule, -1 split
+                            (update kernel, then product kernel), 1 or 2 the
+                            fused kernel with that many rows per thread and
+                            trip (0 = 1); ignored when the tuner decides */
 } pm_opts;
 
 typedef struct {
@@ -287,11 +287,11 @@ int pm_time_kernel(pm_mesh* mesh, int32_t which, int32_t n_launch, hipStream_t s
 
 /*
  * Launch shape of the last pcg_solve on this mesh: rows per tile, threads per
- * block and rows per thread and trip of the fused iteration kernel, 0 for the
- * split schedule (as chosen by the tuner or given in pm_opts).  Returns
- * PM_INVALID_ARG before the first solve.
+ * block and the iteration schedule (pm_opts.iter_shape encoding: 1, 2 or -1),
+ * as chosen by the tuner or given in pm_opts.  Returns PM_INVALID_ARG before
+ * the first solve.
  */
-int pm_last_launch(const pm_mesh* mesh, int32_t* tile_rows, int32_t* block, int32_t* rows);
+int pm_last_launch(const pm_mesh* mesh, int32_t* tile_rows, int32_t* block, int32_t* iter_shape);
 
 #ifdef __cplusplus
 }

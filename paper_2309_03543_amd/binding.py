@@ -41,7 +41,7 @@ class pm_opts(C.Structure):
     _fields_ = [
         ("tol", C.c_double), ("max_it", C.c_int32), ("precision", C.c_int32),
         ("replace_every", C.c_int32), ("x0_is_zero", C.c_int32), ("block", C.c_int32),
-        ("tile_rows", C.c_int32), ("stag_checks", C.c_int32), ("iter_rows", C.c_int32),
+        ("tile_rows", C.c_int32), ("stag_checks", C.c_int32), ("iter_shape", C.c_int32),
     ]
 
 
@@ -222,13 +222,13 @@ def assemble_corrector(mesh: Mesh, kind: int, params: dict, nu: float, dt: float
 
 
 def make_opts(tol=1e-10, max_it=200000, precision=PM_FP64, replace_every=50, x0_is_zero=True,
-              block=0, tile_rows=0, stag_checks=40, iter_rows=0) -> pm_opts:
+              block=0, tile_rows=0, stag_checks=40, iter_shape=0) -> pm_opts:
     o = pm_opts()
     lib().pm_opts_default(C.addressof(o))
     o.tol, o.max_it, o.precision, o.replace_every = tol, max_it, precision, replace_every
     o.x0_is_zero, o.block, o.tile_rows = int(bool(x0_is_zero)), block, tile_rows
     o.stag_checks = stag_checks
-    o.iter_rows = iter_rows
+    o.iter_shape = iter_shape
     return o
 
 
@@ -318,10 +318,10 @@ def pm_time_kernel(mesh: Mesh, which: int, n_launch: int, stream=None):
 
 
 def pm_last_launch(mesh: Mesh) -> dict:
-    """Launch shape (tile rows, block, rows per thread) of the last solve on `mesh`."""
+    """Launch shape (tile rows, block, iteration schedule) of the last solve on `mesh`."""
     v = [C.c_int32() for _ in range(3)]
     _check(lib().pm_last_launch(mesh.handle, *[C.byref(x) for x in v]))
-    return {"tile_rows": v[0].value, "block": v[1].value, "rows": v[2].value}
+    return {"tile_rows": v[0].value, "block": v[1].value, "iter_shape": v[2].value}
 
 
 EXPORTED = [

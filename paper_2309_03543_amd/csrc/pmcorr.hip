@@ -286,8 +286,7 @@ namespace {
 int check_opts(const pm_opts& o) {
   if (!(o.tol > 0.0) || o.max_it < 0 || o.replace_every < 1 ||
       (o.precision != PM_FP64 && o.precision != PM_MIXED) || o.tile_rows < 0 || o.block < 0 ||
-      !(o.iter_rows == -1 || o.iter_rows == 0 || o.iter_rows == 1 || o.iter_rows == 2 ||
-        (o.iter_rows == 4 && o.precision == PM_MIXED))) {
+      o.iter_shape < -1 || o.iter_shape > 2) {
     set_error(PM_INVALID_ARG, "invalid solver options");
     return PM_INVALID_ARG;
   }
@@ -311,7 +310,7 @@ void pm_opts_default(pm_opts* o) {
   o->block = 0;
   o->tile_rows = 0;
   o->stag_checks = 40;
-  o->iter_rows = 0;
+  o->iter_shape = 0;
 }
 
 const char* pm_status_string(int s) {
@@ -556,14 +555,14 @@ int pm_time_kernel(pm_mesh* m, int32_t which, int32_t n_launch, hipStream_t s, d
   return set_time_kernel(m->set, which, n_launch, s, ms, bytes);
 }
 
-int pm_last_launch(const pm_mesh* m, int32_t* tile_rows, int32_t* block, int32_t* rows) {
+int pm_last_launch(const pm_mesh* m, int32_t* tile_rows, int32_t* block, int32_t* iter_shape) {
   if (!m || m->set.last_prec < 0) {
     set_error(PM_INVALID_ARG, "pm_last_launch: null mesh or no solve yet");
     return PM_INVALID_ARG;
   }
   if (tile_rows) *tile_rows = m->set.last_tile;
   if (block) *block = m->set.last_block;
-  if (rows) *rows = m->set.last_rows;
+  if (iter_shape) *iter_shape = m->set.last_rows == 0 ? -1 : m->set.last_rows;
   return PM_OK;
 }
 

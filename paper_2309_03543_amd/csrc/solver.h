@@ -57,7 +57,7 @@ struct SolveSet {
   int g_prec = -1, g_m = -1, g_tile = -1, g_block = -1, g_rows = -1;
   const double* g_val = nullptr;
   // last solve, for the timing hook
-  int last_prec = -1, last_tile = 0, last_block = 256, last_rows = 2;
+  int last_prec = -1, last_tile = 0, last_block = 256, last_rows = 1;
   const double* last_val = nullptr;
   std::vector<void*> allocs;
 };

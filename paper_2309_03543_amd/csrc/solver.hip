@@ -526,8 +526,9 @@ __device__ __forceinline__ void trip_compute(const Trip<V, W, I, R>& T, double a
 // the same expression (same roundings) its own block evaluates, so every block
 // sees the same p'.  Loads are software-pipelined: the first trip's rows and
 // the partials are all in flight before the reduction waits on any of them,
-// and each later trip's rows are loaded while the trip before is computed, so
-// a trip costs one memory round trip (the neighbour gathers), not two.  The
+// and the next trip's rows are loaded while a trip is computed.  (A third
+// trip in flight, and non-temporal loads of the streamed arrays, measured
+// slower on MI355X.)  The
 // system's first tile records the scalars and the iteration count, or the
 // stop status.  `scale` multiplies alpha and beta (1 in solves, 0 when the
 // kernel is timed).
@@ -572,20 +573,19 @@ __global__ void __launch_bounds__(512) k_iter(SetArgs<V, W, I> a, int src, int j
   const double be = rn / rho;
   const double as = al * scale, bs = be * scale;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  // two trip buffers in turn; loads past the tile end are clamped to row r0
-  // and flagged, so they are always in bounds
+  // two trip buffers in turn: while one trip is computed, the next trip's row
+  // loads are in flight.  Loads past the tile end are clamped to row r0 and
+  // flagged, so they are always in bounds.
   for (;;) {
-    base += step;
-    bool more = base < r1;
-    trip_direct<V, W, I, R>(Tb, a, ps, zs, qs, base, r0, r1);
+    trip_direct<V, W, I, R>(Tb, a, ps, zs, qs, base + step, r0, r1);
     trip_compute<V, W, I, R>(Ta, as, bs, pd, zd, qd, xacc, acc);
-    if (!more) break;
-    trip_gather<V, W, I, R>(Tb, ps, zs, qs, r0);
     base += step;
-    more = base < r1;
-    trip_direct<V, W, I, R>(Ta, a, ps, zs, qs, base, r0, r1);
+    if (base >= r1) break;
+    trip_gather<V, W, I, R>(Tb, ps, zs, qs, r0);
+    trip_direct<V, W, I, R>(Ta, a, ps, zs, qs, base + step, r0, r1);
     trip_compute<V, W, I, R>(Tb, as, bs, pd, zd, qd, xacc, acc);
-    if (!more) break;
+    base += step;
+    if (base >= r1) break;
     trip_gather<V, W, I, R>(Ta, ps, zs, qs, r0);
   }
   tile_partial<4>(acc, a.part[src ^ 1] + 4 * (size_t)t);
@@ -878,8 +878,6 @@ struct Ops {
       spmv(S, a, L, s);
     } else if (L.rows == 1) {
       k_iter<V, W, I, 1><<<S.n_tiles, L.block, 0, s>>>(a, src, j, scale);
-    } else if (L.rows == 4 && sizeof(V) == 4) {  // float64 at 4 rows would spill
-      if constexpr (sizeof(V) == 4) k_iter<V, W, I, 4><<<S.n_tiles, L.block, 0, s>>>(a, src, j, scale);
     } else {
       k_iter<V, W, I, 2><<<S.n_tiles, L.block, 0, s>>>(a, src, j, scale);
     }
@@ -908,9 +906,8 @@ struct Ops {
 // Launch shapes tried by the tuner (timing the fused iteration kernel on the
 // real matrix); the choice is cached per problem shape and precision.
 constexpr Launch kCandidates[] = {
-    {512, 256, 1},  {1024, 256, 1}, {1024, 256, 2}, {2048, 256, 2}, {2048, 256, 4},
-    {4096, 256, 4}, {2048, 512, 1}, {2048, 512, 2}, {4096, 512, 2}, {4096, 512, 4},
-    {8192, 512, 4}, {1024, 256, 0}, {2048, 256, 0}, {4096, 256, 0}, {4096, 512, 0},
+    {1024, 256, 1}, {2048, 256, 1}, {2048, 512, 1}, {4096, 512, 1}, {2048, 256, 2},
+    {4096, 512, 2}, {8192, 512, 2}, {2048, 256, 0}, {4096, 256, 0}, {4096, 512, 0},
 };
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int, int>, Launch> g_tuned;
@@ -928,12 +925,11 @@ int tune_launch(SolveSet& S, const double* val64, const double* b, double* x, co
     }
   }
   double best = 1e300;
-  Launch arg = {2048, 256, 2};
+  Launch arg = {2048, 256, 0};
   pm_opts ot = o;
   ot.max_it = INT_MAX;
   for (const Launch& L : kCandidates) {
     if ((long)L.tile * 2 > (long)S.N && L.tile != kCandidates[0].tile) continue;
-    if (L.rows == 4 && sizeof(V) == 8) continue;
     if (int r = build_tiles(S, L.tile)) return r;
     const auto a = make_args<V, W, I>(S, val64, b, x);
     Ops<V, W, I>::start(S, a, ot, L, s);
@@ -965,8 +961,7 @@ int run(SolveSet& S, const double* val64, const double* b, double* x, const pm_o
   Launch L;
   if (o.tile_rows > 0) {
     const int block = o.block > 0 ? std::min(512, std::max(64, (o.block / 64) * 64)) : 256;
-    L = {std::max(kMinTile, o.tile_rows), block,
-         o.iter_rows == -1 ? 0 : (o.iter_rows == 0 ? 1 : o.iter_rows)};
+    L = {std::max(kMinTile, o.tile_rows), block, o.iter_shape < 0 ? 0 : std::max(1, o.iter_shape)};
   } else {
     if (int r = tune_launch<V, W, I>(S, val64, b, x, o, s, &L)) return r;
   }

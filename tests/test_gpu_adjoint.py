@@ -12,6 +12,7 @@ torch = pytest.importorskip("torch")
 from oracle import adjoint as oadj  # noqa: E402
 from oracle import assemble as oasm  # noqa: E402
 from oracle import geometry, ordering  # noqa: E402
+from oracle import pcg as opcg  # noqa: E402
 from synth import workloads  # noqa: E402
 
 pytestmark = pytest.mark.gpu
@@ -65,14 +66,28 @@ def test_adjoint_matches_cpu_adjoint_and_finite_differences(name, kind):
     lam, gs, ge, info = B().pcg_adjoint(c["mesh"], kind, prm, w["nu"], w["dt"], out["val64"], x,
                                         torch.tensor(gL, device=c["dev"]), g_dirichlet=gd, tol=TOL)
     assert info["status"] == 0
-    # CPU FP64 adjoint on the same forward solution
-    o = oadj.adjoint(c["geo"], c["perm"], kind, w["params"], w["nu"], w["dt"], eta, gL,
+    # CPU FP64 adjoint from the oracle's own forward solve (same inputs, no
+    # GPU value enters the oracle)
+    perm = c["perm"]
+    ao = oasm.assemble(c["geo"], perm, kind, w["params"], w["nu"], w["dt"], g)
+    rhs_o = w["rhs"]["cp2" if kind == 2 else "cp1x"] + ao["b_lift"]
+    xp, io = opcg.pcg(ao["A"], rhs_o[perm], tol=TOL)
+    assert io["status"] == opcg.OK
+    eta_o = np.empty(n)
+    eta_o[perm] = xp
+    gL_o = np.zeros(n)
+    gL_o[pr] = 2 * (eta_o[pr] - tg)
+    o = oadj.adjoint(c["geo"], perm, kind, w["params"], w["nu"], w["dt"], eta_o, gL_o,
                      g_dirichlet=g, tol=TOL)
+    # both sides solve forward and adjoint systems to a 1e-11 relative
+    # residual; the solutions agree to ~1e-10 and the bilinear gradients to
+    # a few 1e-9 on this mesh
     lam_g = lam.cpu().numpy()
     assert np.linalg.norm(lam_g - o["lambda"]) <= 1e-8 * np.linalg.norm(o["lambda"])
     for got, key in ((gs, "grad_logk"), (ge, "grad_eps")):
         ref = o[key]
         got = got.cpu().numpy()
+        print(f"{name} kind {kind} {key}: relative difference {np.linalg.norm(got - ref) / np.linalg.norm(ref):.2e}")
         assert np.linalg.norm(got - ref) <= 1e-8 * np.linalg.norm(ref)
     if kind == 2:
         chi = w["params"]["chi"]
@@ -85,7 +100,6 @@ def test_adjoint_matches_cpu_adjoint_and_finite_differences(name, kind):
     # tolerance an iterative solve would need here.
     rp, colx = c["mesh"].export()[1:]
     A0 = sp.csr_matrix((out["val64"].cpu().numpy(), colx, rp), shape=(n, n))
-    perm = c["perm"]
     lift0 = out["b_lift"].cpu().numpy()
 
     def dloss(pp):

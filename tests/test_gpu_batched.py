@@ -93,8 +93,8 @@ def test_batched_iteration_limit():
     assert all(i["status"] == B().PM_MAXIT and i["iters"] == 20 for i in infos)
 
 
-@pytest.mark.parametrize("rows", [-1, 1, 2])
-def test_batched_schedules_agree(rows):
+@pytest.mark.parametrize("shape", [-1, 1, 2])
+def test_batched_schedules_agree(shape):
     # split schedule and fused kernels of several shapes, tiles straddling no
     # system: every system converges to the same solution
     c = batch_case()
@@ -102,7 +102,7 @@ def test_batched_schedules_agree(rows):
     val, b = packed(c)
     x1, i1 = B().pcg_solve_batched(batch, val, b)
     for tile, block in ((256, 64), (1024, 256), (2048, 512)):
-        x2, i2 = B().pcg_solve_batched(batch, val, b, tile_rows=tile, block=block, iter_rows=rows)
+        x2, i2 = B().pcg_solve_batched(batch, val, b, tile_rows=tile, block=block, iter_shape=shape)
         for s in range(len(c["meshes"])):
             sl = slice(int(batch.vec_off[s]), int(batch.vec_off[s + 1]))
             assert i2[s]["status"] == 0 and i2[s]["rel_res_true"] <= 1e-10
