@@ -44,6 +44,22 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def iter_summary(infos):
+    its = [i["iters"] for i in infos]
+    return its if len(its) <= 4 else {"min": min(its), "max": max(its), "sum": sum(its)}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
+
+
 def source_digest() -> str:
     """Digest of the kernel sources, to tell whether stored counter readings
     still describe the kernels in this tree."""
@@ -204,6 +220,25 @@ def main():
     else:
         roof = None
 
+    sequential = None
+    if batch is not None:
+        # the same systems solved one after another with pcg_solve
+        log("timing the batch as sequential single solves")
+        vals = [B.assemble_corrector(m, B.PM_CP2, p, w["nu"], w["dt"])["val64"]
+                for m, p, w in zip(meshes, prms, ws)]
+        for m, v, r in zip(meshes, vals, rhs):  # tune every shape first
+            B.pcg_solve(m, v, r["cp2"])
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for m, v, r in zip(meshes, vals, rhs):
+            _, info = B.pcg_solve(m, v, r["cp2"])
+            if info["status"] != 0:
+                raise RuntimeError(f"sequential solve failed: {info}")
+        torch.cuda.synchronize()
+        seq = time.perf_counter() - t
+        sequential = {"ms": seq * 1e3, "solves_per_s": len(meshes) / seq,
+                      "batched_speedup": value * seq / len(meshes)}
+
     mixed = None
     if not args.no_mixed:
         log("timing mixed steps")
@@ -211,7 +246,7 @@ def main():
         mixed = {
             "solves_per_s": solves_per_step * args.steps / wallm,
             "speedup_vs_fp64": (solves_per_step * args.steps / wallm) / value,
-            "iters": [i["iters"] for i in infm[-1]][:8],
+            "iters": iter_summary(infm[-1]),
             "max_rel_res_true": max(i["rel_res_true"] for i in infm[-1]),
         }
         if tmesh is not None:
@@ -225,12 +260,12 @@ def main():
     if not args.no_cpu_baseline and wl != "batch":
         log("timing the CPU oracle on a bounded sample")
         from oracle import assemble as oasm
-        from oracle import geometry
+        from oracle import geometry, ordering
         from oracle import pcg as opcg
 
-        perm, _, _ = mesh0.export()
         m = w0["mesh"]
         geo = geometry.build(m["xy"], m["tri"], w0["side_tag"])
+        perm = ordering.rcm(geo["nbr"])
         A = oasm.assemble(geo, perm, oasm.CP2, w0["params"], w0["nu"], w0["dt"])["A"]
         b = w0["rhs"]["cp2"][perm]
         k = 50
@@ -250,7 +285,8 @@ def main():
             "kind": "oracle",
             "sample": f"oracle Jacobi-PCG (NumPy/SciPy, single thread) on this workload's CP2 "
                       f"system: {k} iterations at {per_it * 1e3:.2f} ms each, scaled to the "
-                      f"{sum(its)} iterations of one GPU step ({'+'.join(map(str, its))})",
+                      f"{sum(its)} iterations of one GPU step ({'+'.join(map(str, its))}); "
+                      f"host {cpu_model()}, {len(os.sched_getaffinity(0))} cores available",
         }
 
     if args.copy_calibration:
@@ -275,10 +311,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": wname, "n_cells": n_cells, "nnz": nnz, "systems": len(ws),
                    "solves_per_step": solves_per_step, "tol": 1e-10,
-                   "iters": [i["iters"] for i in inf64[-1]][:8]},
+                   "iters": iter_summary(inf64[-1])},
         "roofline": roof,
         "kernels": kern,
         "mixed": mixed,
+        "sequential": sequential,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -62,6 +62,14 @@ extern "C" {
 #define PM_MIXED 1 /* float32 matrix and Krylov vectors; float64 solution,
                       residual replacement and convergence test */
 
+/* preconditioners (both fully data-parallel; the paper's incomplete Cholesky
+   needs sequential triangular sweeps) */
+#define PM_PREC_JACOBI 0    /* z = D^-1 r */
+#define PM_PREC_CHEBYSHEV 1 /* z = p(D^-1 A) D^-1 r: cheb_degree steps of Chebyshev
+                               acceleration of the Jacobi iteration for A z = r from
+                               z = 0 on [2/30, 2]; 2 bounds the spectrum of D^-1 A
+                               (Gershgorin on a weakly diagonally dominant M-matrix) */
+
 typedef struct pm_mesh pm_mesh;
 typedef struct pm_batch pm_batch;
 
@@ -117,6 +125,9 @@ typedef struct {
                             not halved for max(stag_checks * replace_every,
                             k_best) iterations, k_best being the iteration of
                             the last halving (default 40) */
+  int32_t precond;       /* PM_PREC_JACOBI (default) or PM_PREC_CHEBYSHEV */
+  int32_t cheb_degree;   /* Chebyshev polynomial degree, 2..16 (default 4): each
+                            application costs degree - 1 products with A */
   int32_t iter_shape;    /* with tile_rows: the iteration schedule, -1 split
                             (update kernel, then product kernel), 1 or 2 the
                             fused kernel with that many rows per thread and

@@ -4,14 +4,16 @@ TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
 
 The paper solves both corrector systems with PCG (Sec. 3.2.2, after
 eq. CS1_sys_coeff; Sec. 3.2.3, after eq. CS2_sys_coeff, citing
-Hestenes-Stiefel).  Its incomplete-Cholesky preconditioner is replaced by the
-diagonal (Jacobi) one, which needs no sequential triangular sweeps.
+Hestenes-Stiefel).  Its incomplete-Cholesky preconditioner needs sequential
+triangular sweeps; it is replaced by the diagonal (Jacobi) one, z = D^{-1} r,
+or by a Chebyshev polynomial in D^{-1} A (chebyshev_apply), both fully
+data-parallel.
 
 The paper states no tolerance.  The solver is specified as follows (the same
 specification the GPU library implements):
 
   x = x_hi + x_lo (double-double, x_hi = x0, x_lo = 0), x_acc = 0,
-  r = b - A x (true residual), z = D^{-1} r, p = z, rho = r.z
+  r = b - A x (true residual), z = M^{-1} r, p = z, rho = r.z
   iteration k = 1, 2, ...:
     q = A p; alpha = rho / (p.q)   (breakdown if p.q <= 0 or not finite)
     x_acc += alpha p; r -= alpha q
@@ -27,7 +29,7 @@ specification the GPU library implements):
         CG residuals plateau for long stretches on these matrices (over 40%
         of the iterations on a 131k-cell channel), so a shorter window, or a
         gate on the tolerance instead of the floor, stops converging solves.
-    z = D^{-1} r; rho' = r.z; p = z + (rho'/rho) p; rho = rho'
+    z = M^{-1} r; rho' = r.z; p = z + (rho'/rho) p; rho = rho'
 
 Three details make 1e-10 reachable on these matrices, whose
 transmissibilities span decades and whose right-hand sides may be tiny
@@ -45,6 +47,9 @@ import numpy as np
 import scipy.linalg as sla
 
 OK, MAXIT, STAGNATED, BREAKDOWN = 0, 1, 2, -6
+JACOBI, CHEBYSHEV = 0, 1
+CHEB_LMAX = 2.0
+CHEB_RATIO = 30.0
 
 
 def two_sum(a, b):
@@ -52,6 +57,38 @@ def two_sum(a, b):
     s = a + b
     bb = s - a
     return s, (a - (s - bb)) + (b - bb)
+
+
+def chebyshev_interval():
+    """[a, b] the polynomial preconditioner targets.  b = 2 bounds the
+    spectrum of D^-1 A (Gershgorin: in every row of these weakly diagonally
+    dominant M-matrices the off-diagonal magnitudes sum to at most the
+    diagonal); a = b / 30."""
+    b = CHEB_LMAX
+    return b / CHEB_RATIO, b
+
+
+def chebyshev_apply(A, dinv, r, degree):
+    """z = p(D^-1 A) D^-1 r: `degree` steps of Chebyshev acceleration of the
+    Jacobi iteration for A z = r from z = 0 on the interval above (Saad,
+    Iterative Methods for Sparse Linear Systems, 2nd ed., Alg. 12.1, with the
+    residual preconditioned by D); degree - 1 products with A.  The error
+    after the steps is T_k((theta - D^-1 A)/delta) / T_k(theta/delta) times
+    the initial one, so p is positive on (0, b] and the preconditioner SPD."""
+    a, b = chebyshev_interval()
+    theta, delta = 0.5 * (b + a), 0.5 * (b - a)
+    sigma = theta / delta
+    rho = 1.0 / sigma
+    y = dinv * r
+    d = y / theta
+    z = d.copy()
+    for _ in range(degree - 1):
+        y = y - dinv * (A @ d)
+        rho_next = 1.0 / (2.0 * sigma - rho)
+        d = rho_next * rho * d + (2.0 * rho_next / delta) * y
+        z = z + d
+        rho = rho_next
+    return z
 
 
 def true_residual(A, b, x, x_lo=None) -> np.ndarray:
@@ -71,9 +108,10 @@ def true_residual(A, b, x, x_lo=None) -> np.ndarray:
 
 
 def pcg(A, b, tol=1e-10, max_it=100000, replace_every=50, x0=None, record=False,
-        stag_checks=40) -> tuple:
-    """Jacobi PCG with group-update residual replacement every `replace_every`
-    iterations; returns (x, info) with info = iters, status, rel_res_true."""
+        stag_checks=40, precond=JACOBI, degree=4) -> tuple:
+    """PCG with group-update residual replacement every `replace_every`
+    iterations; returns (x, info) with info = iters, status, rel_res_true.
+    precond JACOBI: z = D^-1 r; CHEBYSHEV: z = chebyshev_apply(..., degree)."""
     b = np.asarray(b, np.float64)
     n = b.shape[0]
     x = np.zeros(n) if x0 is None else np.array(x0, np.float64)
@@ -83,13 +121,22 @@ def pcg(A, b, tol=1e-10, max_it=100000, replace_every=50, x0=None, record=False,
     if bnorm == 0.0:
         return np.zeros(n), info
     dinv = 1.0 / A.diagonal()
+    if precond == CHEBYSHEV:
+        if degree < 2:
+            raise ValueError("Chebyshev degree must be at least 2")
+
+        def prec(v):
+            return chebyshev_apply(A, dinv, v, degree)
+    else:
+        def prec(v):
+            return dinv * v
     r = true_residual(A, b, x)
     res = float(np.linalg.norm(r)) / bnorm
     info["rel_res_true"] = res
     if res <= tol:
         return x, info
     xacc = np.zeros(n)
-    z = dinv * r
+    z = prec(r)
     p = z.copy()
     rho = float(r @ z)
     best, k_best = res, 0
@@ -121,7 +168,7 @@ def pcg(A, b, tol=1e-10, max_it=100000, replace_every=50, x0=None, record=False,
                 info.update(iters=k, rel_res_true=res, status=STAGNATED)
                 return x, info
             r = true_residual(A, b, x, x_lo)
-        z = dinv * r
+        z = prec(r)
         rho_new = float(r @ z)
         p = z + (rho_new / rho) * p
         rho = rho_new

@@ -15,6 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpmcorr.so")
 
 PM_OK, PM_MAXIT, PM_STAGNATED = 0, 1, 2
+PM_PREC_JACOBI, PM_PREC_CHEBYSHEV = 0, 1
 PM_INVALID_ARG, PM_BAD_MESH, PM_NOT_DELAUNAY, PM_SINGULAR = -1, -2, -3, -4
 PM_NONFINITE, PM_BREAKDOWN, PM_HIP_ERROR = -5, -6, -7
 PM_CP1X, PM_CP1Y, PM_CP2 = 0, 1, 2
@@ -41,7 +42,8 @@ class pm_opts(C.Structure):
     _fields_ = [
         ("tol", C.c_double), ("max_it", C.c_int32), ("precision", C.c_int32),
         ("replace_every", C.c_int32), ("x0_is_zero", C.c_int32), ("block", C.c_int32),
-        ("tile_rows", C.c_int32), ("stag_checks", C.c_int32), ("iter_shape", C.c_int32),
+        ("tile_rows", C.c_int32), ("stag_checks", C.c_int32), ("precond", C.c_int32),
+        ("cheb_degree", C.c_int32), ("iter_shape", C.c_int32),
     ]
 
 
@@ -222,13 +224,15 @@ def assemble_corrector(mesh: Mesh, kind: int, params: dict, nu: float, dt: float
 
 
 def make_opts(tol=1e-10, max_it=200000, precision=PM_FP64, replace_every=50, x0_is_zero=True,
-              block=0, tile_rows=0, stag_checks=40, iter_shape=0) -> pm_opts:
+              block=0, tile_rows=0, stag_checks=40, iter_shape=0, precond=0,
+              cheb_degree=4) -> pm_opts:
     o = pm_opts()
     lib().pm_opts_default(C.addressof(o))
     o.tol, o.max_it, o.precision, o.replace_every = tol, max_it, precision, replace_every
     o.x0_is_zero, o.block, o.tile_rows = int(bool(x0_is_zero)), block, tile_rows
     o.stag_checks = stag_checks
     o.iter_shape = iter_shape
+    o.precond, o.cheb_degree = precond, cheb_degree
     return o
 
 

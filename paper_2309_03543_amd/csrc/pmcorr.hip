@@ -286,7 +286,9 @@ namespace {
 int check_opts(const pm_opts& o) {
   if (!(o.tol > 0.0) || o.max_it < 0 || o.replace_every < 1 ||
       (o.precision != PM_FP64 && o.precision != PM_MIXED) || o.tile_rows < 0 || o.block < 0 ||
-      o.iter_shape < -1 || o.iter_shape > 2) {
+      o.iter_shape < -1 || o.iter_shape > 2 ||
+      (o.precond != PM_PREC_JACOBI && o.precond != PM_PREC_CHEBYSHEV) ||
+      (o.precond == PM_PREC_CHEBYSHEV && (o.cheb_degree < 2 || o.cheb_degree > 16))) {
     set_error(PM_INVALID_ARG, "invalid solver options");
     return PM_INVALID_ARG;
   }
@@ -311,6 +313,8 @@ void pm_opts_default(pm_opts* o) {
   o->tile_rows = 0;
   o->stag_checks = 40;
   o->iter_shape = 0;
+  o->precond = PM_PREC_JACOBI;
+  o->cheb_degree = 4;
 }
 
 const char* pm_status_string(int s) {

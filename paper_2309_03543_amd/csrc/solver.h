@@ -17,6 +17,7 @@ struct SysState {
   double bnorm2, tol2;      // ||b||^2 and tol^2 ||b||^2
   double res2;              // last true residual ||b - A x_hi||^2
   double best_res2;         // smallest res2 seen (stagnation test)
+  double rho_ring[2];       // r.z of iterations k (slot k & 1), Chebyshev schedule
   int32_t iter;             // completed iterations
   int32_t iter_base;        // completed iterations at the start of the current chunk
   int32_t max_it;
@@ -47,6 +48,8 @@ struct SolveSet {
   double *dp = nullptr, *x64 = nullptr, *xlo = nullptr, *b64 = nullptr;
   void* xacc = nullptr;
   void *p[2] = {nullptr, nullptr}, *z[2] = {nullptr, nullptr}, *q[2] = {nullptr, nullptr};
+  void* y = nullptr;                       // D'^{-1} r (Chebyshev schedule)
+  void* zc[3] = {nullptr, nullptr, nullptr};  // Chebyshev iterates, rotating
   double *part[2] = {nullptr, nullptr}, *part3 = nullptr;
   SysState* ss = nullptr;
   SysState* h_ss = nullptr;  // pinned, 3 slots of n_sys states
@@ -54,10 +57,10 @@ struct SolveSet {
   hipEvent_t ev[2] = {nullptr, nullptr};
   hipEvent_t tev[2] = {nullptr, nullptr};
   hipGraphExec_t graph = nullptr;
-  int g_prec = -1, g_m = -1, g_tile = -1, g_block = -1, g_rows = -1;
+  int g_prec = -1, g_m = -1, g_tile = -1, g_block = -1, g_rows = -1, g_pc = -1;
   const double* g_val = nullptr;
   // last solve, for the timing hook
-  int last_prec = -1, last_tile = 0, last_block = 256, last_rows = 1;
+  int last_prec = -1, last_tile = 0, last_block = 256, last_rows = 1, last_pc = 0;
   const double* last_val = nullptr;
   std::vector<void*> allocs;
 };

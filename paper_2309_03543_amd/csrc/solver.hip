@@ -69,6 +69,8 @@ struct SetArgs {
   V* q[2];
   double* part[2];  // [tile][4] product partials, alternating with the buffers
   double* part3;    // [tile][4] residual partials
+  V* y;             // D'^{-1} r (Chebyshev schedule)
+  V* zc[3];         // Chebyshev iterates, rotating
   SysState* ss;
 };
 
@@ -112,6 +114,7 @@ __global__ void k_sys_init(SysState* ss, int n_sys, int max_it, int stag_it) {
   SysState z{};
   z.max_it = max_it;
   z.stag_it = stag_it;
+  z.rho_ring[0] = z.rho_ring[1] = INFINITY;  // first Chebyshev direction: beta = 0
   ss[s] = z;
 }
 
@@ -163,6 +166,8 @@ __global__ void __launch_bounds__(1024) k_prep(SetArgs<V, W, I> a, int x0_zero) 
     a.x64[i] = xi;
     a.xlo[i] = 0.0;
     a.xacc[i] = V(0);
+    a.p[0][i] = V(0);
+    a.p[1][i] = V(0);
     acc[0] += bi * bi;
     acc[1] += xi * xi;
   }
@@ -199,8 +204,10 @@ __global__ void k_sys_start(SetArgs<V, W, I> a, double tol) {
 //   mode 0 (start):   z = r_dd/d', p = z   (buffer 0)
 //   mode 1 (replace): z = r_dd/d'          (buffer 0)
 //   mode 2 (final):   norms only, also for stopped systems
+// With inv_theta > 0 (Chebyshev schedule) modes 0 and 1 write y = r_dd/d' and
+// the first Chebyshev iterate z_1 = y / theta instead.
 template <typename V, typename W, typename I>
-__global__ void __launch_bounds__(1024) k_resid(SetArgs<V, W, I> a, int mode) {
+__global__ void __launch_bounds__(1024) k_resid(SetArgs<V, W, I> a, int mode, double inv_theta) {
   const int t = xcd_block(blockIdx.x, gridDim.x);
   const int s = a.tile_sys[t];
   if (mode != 2 && a.ss[s].done) return;
@@ -213,10 +220,15 @@ __global__ void __launch_bounds__(1024) k_resid(SetArgs<V, W, I> a, int mode) {
     if (mode != 2) {
       const double d = a.dp[i];
       const V zv = (V)(rd / d);
-      a.z[0][i] = zv;
-      if (mode == 0) a.p[0][i] = zv;
-      const double zd = (double)zv;
-      acc[1] += d * zd * zd;
+      if (inv_theta > 0.0) {
+        a.y[i] = zv;
+        a.zc[1][i] = (V)((double)zv * inv_theta);
+      } else {
+        a.z[0][i] = zv;
+        if (mode == 0) a.p[0][i] = zv;
+        const double zd = (double)zv;
+        acc[1] += d * zd * zd;
+      }
     }
   }
   tile_partial<3>(acc, a.part3 + 4 * (size_t)t);
@@ -227,7 +239,7 @@ __global__ void __launch_bounds__(1024) k_resid(SetArgs<V, W, I> a, int mode) {
 // rounding floor u || |A||x| || and has not halved for max(stag_it, k_best)
 // iterations); the scalars of the next direction.
 template <typename V, typename W, typename I>
-__global__ void k_sys_check(SetArgs<V, W, I> a, int mode) {
+__global__ void k_sys_check(SetArgs<V, W, I> a, int mode, int cheb) {
   const int s = blockIdx.x;
   SysState& S = a.ss[s];
   if (mode != 2 && S.done) return;
@@ -244,7 +256,7 @@ __global__ void k_sys_check(SetArgs<V, W, I> a, int mode) {
     S.status = PM_OK;
     S.done = 1;
   } else if (mode == 0) {
-    S.rho = r[1];
+    if (!cheb) S.rho = r[1];
     S.best_res2 = r[0];
     S.k_best = S.iter;
   } else {
@@ -258,8 +270,10 @@ __global__ void k_sys_check(SetArgs<V, W, I> a, int mode) {
       S.status = PM_STAGNATED;
       S.done = 1;
     } else {
-      S.beta = r[1] / S.rho;
-      S.rho = r[1];
+      if (!cheb) {  // the Chebyshev direction kernel forms its own beta
+        S.beta = r[1] / S.rho;
+        S.rho = r[1];
+      }
       S.iter_base = S.iter;
     }
   }
@@ -667,6 +681,209 @@ __global__ void __launch_bounds__(1024) k_update(SetArgs<V, W, I> a, int j, doub
   }
 }
 
+// ---------------------------------------------------------------------------
+// Chebyshev-preconditioned schedule.  z = p(D'^{-1} A) D'^{-1} r replaces
+// z = D'^{-1} r: y = D'^{-1} r is kept apart, z_1 = y / theta, and
+//   z_{i+1} = z_i + omega_i (z_i - z_{i-1}) + gamma_i (y - D'^{-1} A z_i)
+// (the three-term form of Chebyshev acceleration from z_0 = 0; the host
+// computes omega_i, gamma_i).  Per CG iteration: k_cheb_dir (new direction
+// and its product), k_cheb_update (x_acc, y, z_1) and degree - 1 steps
+// k_cheb_step, the last of which forms the partials of rho = r.z.
+// ---------------------------------------------------------------------------
+
+// Iteration k = iter_base + j: rho_k from the last step's partials (part[1]),
+// beta = rho_k / rho_{k-1} (rho_0 = inf: beta = 0), p = z + beta p_old and
+// q~ = D'^{-1} A p with the tile partials of p.q in part[0].  A neighbour's
+// new p is recomputed from its z and old p with the same expression.
+template <typename V, typename W, typename I>
+__global__ void __launch_bounds__(1024) k_cheb_dir(SetArgs<V, W, I> a, int zb, int j) {
+  const int t = xcd_block(blockIdx.x, gridDim.x);
+  const int s = a.tile_sys[t];
+  SysState& S = a.ss[s];
+  if (S.done) return;
+  const int r0 = a.tile_r0[t], r1 = a.tile_r1[t];
+  const int t0 = a.sys_tile0[s], t1 = a.sys_tile0[s + 1];
+  const int k = S.iter_base + j;
+  double r[4];
+  sum_range<4>(a.part[1], t0, t1, r);
+  const double rho = r[0];
+  const bool first = t == t0 && threadIdx.x == 0;
+  if (!(rho > 0.0) || !isfinite(rho)) {  // zero residual, or a preconditioner breakdown
+    if (first) {
+      S.status = rho == 0.0 ? PM_OK : PM_BREAKDOWN;
+      S.done = 1;
+    }
+    return;
+  }
+  const double be = rho / S.rho_ring[(k - 1) & 1];
+  const int N = a.N;
+  const V* __restrict__ z = a.zc[zb];
+  const V* __restrict__ po = a.p[(k - 1) & 1];
+  V* __restrict__ pn = a.p[k & 1];
+  V* __restrict__ q = a.q[0];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int base = r0 + threadIdx.x; base < r1; base += kUnroll * blockDim.x) {
+    int row[kUnroll];
+    W w0[kUnroll], w1[kUnroll], w2[kUnroll], cc[kUnroll];
+    I i0[kUnroll], i1[kUnroll], i2[kUnroll];
+    V zv[kUnroll], pv[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int i0r = base + u * (int)blockDim.x;
+      row[u] = i0r < r1 ? i0r : -1;
+      const int i = i0r < r1 ? i0r : r0;
+      w0[u] = a.w[i];
+      w1[u] = a.w[(size_t)N + i];
+      w2[u] = a.w[2 * (size_t)N + i];
+      i0[u] = a.idx[i];
+      i1[u] = a.idx[(size_t)N + i];
+      i2[u] = a.idx[2 * (size_t)N + i];
+      cc[u] = a.c[i];
+      zv[u] = z[i];
+      pv[u] = po[i];
+    }
+    double g[3][kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int i = row[u] >= 0 ? row[u] : r0;
+      const int js[3] = {col_of<I>(i, i0[u]), col_of<I>(i, i1[u]), col_of<I>(i, i2[u])};
+#pragma unroll
+      for (int e = 0; e < 3; ++e) g[e][u] = (double)(V)((double)z[js[e]] + be * (double)po[js[e]]);
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      if (row[u] < 0) continue;
+      const V pnv = (V)((double)zv[u] + be * (double)pv[u]);
+      pn[row[u]] = pnv;
+      const double pi = (double)pnv, ci = (double)cc[u];
+      double yv = ci * pi;
+      yv += (double)w0[u] * (pi - g[0][u]);
+      yv += (double)w1[u] * (pi - g[1][u]);
+      yv += (double)w2[u] * (pi - g[2][u]);
+      const double d = ((ci + (double)w0[u]) + (double)w1[u]) + (double)w2[u];
+      const V qv = (V)(yv / d);
+      q[row[u]] = qv;
+      acc[0] += pi * (d * (double)qv);
+    }
+  }
+  tile_partial<4>(acc, a.part[0] + 4 * (size_t)t);
+  if (first) {
+    S.rho_ring[k & 1] = rho;
+    S.rho = rho;
+    S.beta = be;
+  }
+}
+
+// Iteration k = iter_base + j: alpha = rho_k / p.q; x_acc += alpha p,
+// y -= alpha q~ and z_1 = y / theta, or on the chunk's last iteration (FLUSH)
+// (x_hi, x_lo) += x_acc + alpha p, y and z_1 then coming from the true residual.
+template <typename V, typename W, typename I, bool FLUSH>
+__global__ void __launch_bounds__(1024) k_cheb_update(SetArgs<V, W, I> a, int j,
+                                                      double inv_theta) {
+  const int t = xcd_block(blockIdx.x, gridDim.x);
+  const int s = a.tile_sys[t];
+  SysState& S = a.ss[s];
+  if (S.done) return;
+  const int r0 = a.tile_r0[t], r1 = a.tile_r1[t];
+  const int t0 = a.sys_tile0[s], t1 = a.sys_tile0[s + 1];
+  double r[4];
+  sum_range<4>(a.part[0], t0, t1, r);
+  const bool first = t == t0 && threadIdx.x == 0;
+  const int k = S.iter_base + j;
+  const double pq = r[0], rho = S.rho_ring[k & 1];
+  if (const int stop = stop_code(k, S.max_it, pq, rho)) {
+    if (first) {
+      S.status = stop == 100 ? PM_OK : stop;
+      S.done = 1;
+    }
+    return;
+  }
+  const double al = rho / pq;
+  const V* __restrict__ p = a.p[k & 1];
+  for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+    const double pi = (double)p[i];
+    if (FLUSH) {
+      double hi = a.x64[i], lo = a.xlo[i];
+      dd_add(hi, lo, (double)a.xacc[i] + al * pi);
+      a.x64[i] = hi;
+      a.xlo[i] = lo;
+      a.xacc[i] = V(0);
+    } else {
+      a.xacc[i] = (V)((double)a.xacc[i] + al * pi);
+      const V yv = (V)((double)a.y[i] - al * (double)a.q[0][i]);
+      a.y[i] = yv;
+      a.zc[1][i] = (V)((double)yv * inv_theta);
+    }
+  }
+  if (first) {
+    S.alpha = al;
+    S.iter = k;
+  }
+}
+
+// One Chebyshev step z_out = z_in + omega (z_in - z_prev) + gamma (y - D'^{-1}
+// A z_in) (z_prev = 0 when from_zero); the last step of an application also
+// forms the tile partials of rho = r.z = sum d' y z_out in part[1].
+template <typename V, typename W, typename I>
+__global__ void __launch_bounds__(1024) k_cheb_step(SetArgs<V, W, I> a, int zin, int zprev,
+                                                    int zout, double omega, double gamma,
+                                                    int from_zero, int last) {
+  const int t = xcd_block(blockIdx.x, gridDim.x);
+  const int s = a.tile_sys[t];
+  if (a.ss[s].done) return;
+  const int r0 = a.tile_r0[t], r1 = a.tile_r1[t];
+  const int N = a.N;
+  const V* __restrict__ zi_ = a.zc[zin];
+  const V* __restrict__ zp_ = a.zc[zprev];
+  V* __restrict__ zo_ = a.zc[zout];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int base = r0 + threadIdx.x; base < r1; base += kUnroll * blockDim.x) {
+    int row[kUnroll];
+    W w0[kUnroll], w1[kUnroll], w2[kUnroll], cc[kUnroll];
+    I i0[kUnroll], i1[kUnroll], i2[kUnroll];
+    V zv[kUnroll], zp[kUnroll], yv[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int i0r = base + u * (int)blockDim.x;
+      row[u] = i0r < r1 ? i0r : -1;
+      const int i = i0r < r1 ? i0r : r0;
+      w0[u] = a.w[i];
+      w1[u] = a.w[(size_t)N + i];
+      w2[u] = a.w[2 * (size_t)N + i];
+      i0[u] = a.idx[i];
+      i1[u] = a.idx[(size_t)N + i];
+      i2[u] = a.idx[2 * (size_t)N + i];
+      cc[u] = a.c[i];
+      zv[u] = zi_[i];
+      zp[u] = from_zero ? V(0) : zp_[i];
+      yv[u] = a.y[i];
+    }
+    V g0[kUnroll], g1[kUnroll], g2[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int i = row[u] >= 0 ? row[u] : r0;
+      g0[u] = zi_[col_of<I>(i, i0[u])];
+      g1[u] = zi_[col_of<I>(i, i1[u])];
+      g2[u] = zi_[col_of<I>(i, i2[u])];
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      if (row[u] < 0) continue;
+      const double zi = (double)zv[u], ci = (double)cc[u];
+      double az = ci * zi;
+      az += (double)w0[u] * (zi - (double)g0[u]);
+      az += (double)w1[u] * (zi - (double)g1[u]);
+      az += (double)w2[u] * (zi - (double)g2[u]);
+      const double d = ((ci + (double)w0[u]) + (double)w1[u]) + (double)w2[u];
+      const double yi = (double)yv[u];
+      const V zo = (V)(zi + omega * (zi - (double)zp[u]) + gamma * (yi - az / d));
+      zo_[row[u]] = zo;
+      acc[0] += d * yi * (double)zo;
+    }
+  }
+  if (last) tile_partial<4>(acc, a.part[1] + 4 * (size_t)t);
+}
+
 // Last iteration of a chunk (k = iter_base + m): the same scalars from the
 // partials in part[src], then (x_hi, x_lo) += x_acc + alpha p and x_acc = 0;
 // z and p are rebuilt from the true residual afterwards.
@@ -840,8 +1057,38 @@ SetArgs<V, W, I> make_args(SolveSet& S, const double* val, const double* b, doub
     a.part[k] = S.part[k];
   }
   a.part3 = S.part3;
+  a.y = (V*)S.y;
+  for (int k = 0; k < 3; ++k) a.zc[k] = (V*)S.zc[k];
   a.ss = S.ss;
   return a;
+}
+
+// Chebyshev coefficients: the interval [b / 30, b] with b = 2 (Gershgorin
+// bound of D^{-1} A), theta and delta its centre and half width; step i of
+// the three-term form uses omega_i = rho_{i-1} rho_{i-2} and gamma_i =
+// 2 rho_{i-1} / delta with rho_0 = delta / theta, rho_i = 1 / (2 theta /
+// delta - rho_{i-1}).
+constexpr int kMaxChebDegree = 16;
+struct Cheb {
+  int degree = 0;
+  double inv_theta = 0.0;
+  double omega[kMaxChebDegree + 1] = {}, gamma[kMaxChebDegree + 1] = {};
+};
+
+Cheb make_cheb(int degree) {
+  Cheb C;
+  C.degree = degree;
+  const double b = 2.0, a = b / 30.0;
+  const double theta = 0.5 * (b + a), delta = 0.5 * (b - a), sigma = theta / delta;
+  C.inv_theta = 1.0 / theta;
+  double rho[kMaxChebDegree + 1];
+  rho[0] = 1.0 / sigma;
+  for (int i = 1; i <= kMaxChebDegree; ++i) rho[i] = 1.0 / (2.0 * sigma - rho[i - 1]);
+  for (int i = 2; i <= degree; ++i) {
+    C.omega[i] = rho[i - 1] * rho[i - 2];
+    C.gamma[i] = 2.0 * rho[i - 1] / delta;
+  }
+  return C;
 }
 
 // Launch shape: rows per tile, threads per block, rows per thread and trip of
@@ -862,9 +1109,10 @@ struct Ops {
     k_sys_start<V, W, I><<<S.n_sys, 256, 0, s>>>(a, o.tol);
     resid(S, a, 0, L, s);
   }
-  static void resid(SolveSet& S, const A& a, int mode, const Launch& L, hipStream_t s) {
-    k_resid<V, W, I><<<S.n_tiles, L.block, 0, s>>>(a, mode);
-    k_sys_check<V, W, I><<<S.n_sys, 256, 0, s>>>(a, mode);
+  static void resid(SolveSet& S, const A& a, int mode, const Launch& L, hipStream_t s,
+                    double inv_theta = 0.0) {
+    k_resid<V, W, I><<<S.n_tiles, L.block, 0, s>>>(a, mode, inv_theta);
+    k_sys_check<V, W, I><<<S.n_sys, 256, 0, s>>>(a, mode, inv_theta > 0.0 ? 1 : 0);
   }
   static void spmv(SolveSet& S, const A& a, const Launch& L, hipStream_t s) {
     k_spmv<V, W, I><<<S.n_tiles, L.block, 0, s>>>(a);
@@ -895,6 +1143,40 @@ struct Ops {
     k_update_flush<V, W, I><<<S.n_tiles, L.block, 0, s>>>(a, src, m);
     resid(S, a, 1, L, s);
     k_pdir<V, W, I><<<S.n_tiles, L.block, 0, s>>>(a, src);
+  }
+  // Chebyshev schedule (see k_cheb_dir).  degree - 1 steps from z_1 build z
+  // in buffer degree % 3; the last one forms the partials of r.z.
+  static void cheb_steps(SolveSet& S, const A& a, const Launch& L, hipStream_t s,
+                         const Cheb& C) {
+    for (int i = 2; i <= C.degree; ++i)
+      k_cheb_step<V, W, I><<<S.n_tiles, L.block, 0, s>>>(a, (i - 1) % 3, (i - 2) % 3, i % 3,
+                                                         C.omega[i], C.gamma[i], i == 2 ? 1 : 0,
+                                                         i == C.degree ? 1 : 0);
+  }
+  static void cheb_start(SolveSet& S, const A& a, const pm_opts& o, const Launch& L,
+                         hipStream_t s, const Cheb& C) {
+    const int checks = o.stag_checks > 0 ? o.stag_checks : 40;
+    const long win = (long)checks * o.replace_every;
+    k_sys_init<<<(S.n_sys + 63) / 64, 64, 0, s>>>(S.ss, S.n_sys, o.max_it,
+                                                  (int)std::min<long>(win, INT_MAX));
+    k_prep<V, W, I><<<S.n_tiles, L.block, 0, s>>>(a, o.x0_is_zero);
+    k_sys_start<V, W, I><<<S.n_sys, 256, 0, s>>>(a, o.tol);
+    resid(S, a, 0, L, s, C.inv_theta);
+    cheb_steps(S, a, L, s, C);
+  }
+  static void cheb_chunk(SolveSet& S, const A& a, int m, const Launch& L, hipStream_t s,
+                         const Cheb& C) {
+    for (int j = 1; j <= m; ++j) {
+      k_cheb_dir<V, W, I><<<S.n_tiles, L.block, 0, s>>>(a, C.degree % 3, j);
+      if (j < m) {
+        k_cheb_update<V, W, I, false><<<S.n_tiles, L.block, 0, s>>>(a, j, C.inv_theta);
+        cheb_steps(S, a, L, s, C);
+      } else {
+        k_cheb_update<V, W, I, true><<<S.n_tiles, L.block, 0, s>>>(a, j, C.inv_theta);
+      }
+    }
+    resid(S, a, 1, L, s, C.inv_theta);
+    cheb_steps(S, a, L, s, C);
   }
   static void finish(SolveSet& S, const A& a, const Launch& L, hipStream_t s) {
     k_flush<V, W, I><<<S.n_tiles, L.block, 0, s>>>(a);
@@ -973,18 +1255,24 @@ int run(SolveSet& S, const double* val64, const double* b, double* x, const pm_o
   S.last_rows = L.rows;
   S.last_val = val64;
 
-  O::start(S, a, o, L, s);
+  const bool cheb = o.precond == PM_PREC_CHEBYSHEV;
+  const Cheb C = make_cheb(cheb ? o.cheb_degree : 0);
+  const int pc = cheb ? 100 + o.cheb_degree : 0;
+  S.last_pc = pc;
+  if (cheb) O::cheb_start(S, a, o, L, s, C);
+  else O::start(S, a, o, L, s);
   PS_HIP(hipGetLastError());
 
   if (!S.graph || S.g_prec != o.precision || S.g_m != o.replace_every || S.g_tile != L.tile ||
-      S.g_block != L.block || S.g_rows != L.rows || S.g_val != val64) {
+      S.g_block != L.block || S.g_rows != L.rows || S.g_pc != pc || S.g_val != val64) {
     if (S.graph) {
       (void)hipGraphExecDestroy(S.graph);
       S.graph = nullptr;
     }
     hipGraph_t g = nullptr;
     PS_HIP(hipStreamBeginCapture(S.cap, hipStreamCaptureModeThreadLocal));
-    O::chunk(S, a, o.replace_every, L, S.cap);
+    if (cheb) O::cheb_chunk(S, a, o.replace_every, L, S.cap, C);
+    else O::chunk(S, a, o.replace_every, L, S.cap);
     PS_HIP(hipStreamEndCapture(S.cap, &g));
     PS_HIP(hipGraphInstantiate(&S.graph, g, nullptr, nullptr, 0));
     (void)hipGraphDestroy(g);
@@ -993,6 +1281,7 @@ int run(SolveSet& S, const double* val64, const double* b, double* x, const pm_o
     S.g_tile = L.tile;
     S.g_block = L.block;
     S.g_rows = L.rows;
+    S.g_pc = pc;
     S.g_val = val64;
   }
 
@@ -1074,7 +1363,8 @@ int set_init(SolveSet& S, const std::vector<int>& rows, int64_t nnz, int index_b
   if ((r = salloc(S, &S.dp, N)) || (r = salloc(S, &S.x64, N)) || (r = salloc(S, &S.xlo, N)) ||
       (r = salloc(S, &S.b64, N)))
     return r;
-  void** vecs[] = {&S.xacc, &S.p[0], &S.p[1], &S.z[0], &S.z[1], &S.q[0], &S.q[1]};
+  void** vecs[] = {&S.xacc, &S.p[0], &S.p[1], &S.z[0], &S.z[1], &S.q[0],
+                   &S.q[1], &S.y,    &S.zc[0], &S.zc[1], &S.zc[2]};
   for (void** v : vecs) {
     if ((r = salloc(S, &d, N))) return r;
     *v = d;
@@ -1123,7 +1413,7 @@ int time_kernel(SolveSet& S, int which, int n_launch, hipStream_t s, double* ms)
   for (int r = 0; r < n_launch; ++r) {
     if (which == 0) Ops<V, W, I>::spmv(S, a, L, s);
     else if (which == 1) Ops<V, W, I>::iter(S, a, r & 1, 1, L, s, 0.0);
-    else k_resid<V, W, I><<<S.n_tiles, L.block, 0, s>>>(a, 2);
+    else k_resid<V, W, I><<<S.n_tiles, L.block, 0, s>>>(a, 2, 0.0);
   }
   PS_HIP(hipEventRecord(S.tev[1], s));
   PS_HIP(hipGetLastError());
@@ -1137,7 +1427,7 @@ int time_kernel(SolveSet& S, int which, int n_launch, hipStream_t s, double* ms)
 
 int set_time_kernel(SolveSet& S, int which, int n_launch, hipStream_t s, double* ms,
                     double* bytes) {
-  if (S.last_prec < 0 || which < 0 || which > 2 || n_launch < 1) {
+  if (S.last_prec < 0 || which < 0 || which > 2 || n_launch < 1 || (which == 1 && S.last_pc)) {
     set_error(PM_INVALID_ARG, "pm_time_kernel: no solve to time or bad kernel id");
     return PM_INVALID_ARG;
   }

@@ -320,9 +320,9 @@ def channel_mesh(n_rows: int, seed: int, jitter: float = 0.15, bands=(0.05, 0.10
 
 def unit_square_lattice(target_cells: int, seed: int, jitter: float = 0.15) -> dict:
     """Jittered triangular lattice on the unit square with about target_cells triangles."""
-    # a triangular lattice with r rows has about (2/sqrt(3)) r^2 columns-rows products,
-    # i.e. about 2 * (2/sqrt(3)) r^2 triangles on the unit square
-    n_rows = max(2, int(round(math.sqrt(target_cells * math.sqrt(3.0) / 4.0))))
+    # r rows of spacing sqrt(3)/2 h on the unit square give h = 2 / (sqrt(3) r),
+    # about 1/h points per row and two triangles per point: sqrt(3) r^2 triangles
+    n_rows = max(2, int(round(math.sqrt(target_cells / math.sqrt(3.0)))))
     return graded_lattice(n_rows, 1.0, 1.0, seed, jitter=jitter)
 
 

@@ -108,3 +108,22 @@ def test_batched_schedules_agree(shape):
             assert i2[s]["status"] == 0 and i2[s]["rel_res_true"] <= 1e-10
             assert torch.linalg.norm(x2[sl] - x1[sl]) <= 1e-9 * torch.linalg.norm(x1[sl])
             assert abs(i2[s]["iters"] - i1[s]["iters"]) <= 100
+
+
+def test_batched_chebyshev_matches_single_solves():
+    c = batch_case()
+    batch = c["batch"]
+    val, b = packed(c)
+    cheb = dict(precond=B().PM_PREC_CHEBYSHEV, cheb_degree=4)
+    for precision in (0, 1):
+        x, infos = B().pcg_solve_batched(batch, val, b, precision=precision, **cheb)
+        for s, mesh in enumerate(c["meshes"]):
+            sl = slice(int(batch.vec_off[s]), int(batch.vec_off[s + 1]))
+            x1, i1 = B().pcg_solve(mesh, c["vals"][s], c["bs"][s], precision=precision, **cheb)
+            assert infos[s]["status"] == 0 and i1["status"] == 0
+            assert abs(infos[s]["iters"] - i1["iters"]) <= 50
+            perm, A, bo = c["oracle"][s]
+            xg = x[sl].cpu().numpy()[perm]
+            assert opcg.rel_residual(A, bo, xg) <= 1e-10
+            ref = x1.cpu().numpy()[perm]
+            assert np.linalg.norm(xg - ref) <= 1e-9 * np.linalg.norm(ref)

@@ -104,7 +104,8 @@ def solve_both(name, kind, precision, rhs=None, **kw):
     x, info = B().pcg_solve(c["mesh"], val, bt, precision=precision, **kw)
     torch.cuda.synchronize()
     xo, io = opcg.pcg(A, to_perm(c, b), tol=kw.get("tol", 1e-10), max_it=kw.get("max_it", 100000),
-                      replace_every=kw.get("replace_every", 50), stag_checks=kw.get("stag_checks", 40))
+                      replace_every=kw.get("replace_every", 50), stag_checks=kw.get("stag_checks", 40),
+                      precond=kw.get("precond", 0), degree=kw.get("cheb_degree", 4))
     return c, A, to_perm(c, b), to_perm(c, x.cpu().numpy()), info, xo, io
 
 
@@ -142,6 +143,34 @@ def test_replacement_period_odd_and_even(m):
         assert np.linalg.norm(xg - xo) <= 1e-9 * np.linalg.norm(xo)
         if prec == 0:
             assert abs(info["iters"] - io["iters"]) <= max(2 * m, 0.02 * io["iters"])
+
+
+@pytest.mark.parametrize("name,kind,degree", [("c1", "cp2", 4), ("chan", "cp2", 2), ("chan", "cp2", 8),
+                                              ("chan", "cp1x", 4), ("aniso", "cp2", 5), ("tiny", "cp2", 3)])
+def test_chebyshev_solve_matches_oracle(name, kind, degree):
+    cheb = dict(precond=B().PM_PREC_CHEBYSHEV, cheb_degree=degree)
+    c, A, b, xg, info, xo, io = solve_both(name, kind, 0, **cheb)
+    assert info["status"] == 0 and io["status"] == 0
+    res = opcg.rel_residual(A, b, xg)
+    assert res <= 1e-10 and abs(info["rel_res_true"] - res) <= 1e-2 * res + 1e-16
+    assert np.linalg.norm(xg - xo) <= 1e-9 * np.linalg.norm(xo)
+    assert abs(info["iters"] - io["iters"]) <= max(50, 0.02 * io["iters"])
+    # mixed precision with the same preconditioner reaches the same accuracy
+    c, A, b, xm, im, _, _ = solve_both(name, kind, 1, **cheb)
+    assert im["status"] == 0 and opcg.rel_residual(A, b, xm) <= 1e-10
+    assert np.linalg.norm(xm - xo) <= 1e-9 * np.linalg.norm(xo)
+    print(f"chebyshev {degree} {name} {kind}: iters {info['iters']} (oracle {io['iters']}), mixed {im['iters']}")
+
+
+@pytest.mark.parametrize("m", [1, 7])
+def test_chebyshev_odd_replacement_periods_and_limit(m):
+    cheb = dict(precond=B().PM_PREC_CHEBYSHEV, cheb_degree=3, replace_every=m)
+    c, A, b, xg, info, xo, io = solve_both("chan", "cp2", 0, **cheb)
+    assert info["status"] == 0 and opcg.rel_residual(A, b, xg) <= 1e-10
+    assert np.linalg.norm(xg - xo) <= 1e-9 * np.linalg.norm(xo)
+    c, A, b, xg, info, xo, io = solve_both("c1", "cp2", 0, max_it=11, **cheb)
+    assert info["status"] == B().PM_MAXIT and info["iters"] == 11 and io["iters"] == 11
+    assert np.linalg.norm(xg - xo) <= 1e-10 * np.linalg.norm(xo)
 
 
 def test_iteration_limit_and_partial_iterate():
@@ -210,6 +239,19 @@ def test_error_statuses():
     with pytest.raises(Bm.PMError) as e:
         Bm.assemble_corrector(mesh2, Bm.PM_CP2, c["prm"], w["nu"], w["dt"])
     assert e.value.status == Bm.PM_SINGULAR
+
+
+def test_chebyshev_options_are_checked():
+    c = case("tiny")
+    w = c["w"]
+    val = B().assemble_corrector(c["mesh"], B().PM_CP2, c["prm"], w["nu"], w["dt"])["val64"]
+    b = torch.tensor(w["rhs"]["cp2"], device=c["dev"])
+    for deg in (1, 17):
+        with pytest.raises(B().PMError) as e:
+            B().pcg_solve(c["mesh"], val, b, precond=B().PM_PREC_CHEBYSHEV, cheb_degree=deg)
+        assert e.value.status == -1
+    with pytest.raises(B().PMError):
+        B().pcg_solve(c["mesh"], val, b, precond=2)
 
 
 def test_unreachable_tolerance_stagnates_like_the_oracle():

@@ -80,3 +80,43 @@ def test_unreachable_tolerance_reports_stagnation():
     x, info = pcg.pcg(A, b, tol=1e-19, max_it=50000, stag_checks=10)
     assert info["status"] == pcg.STAGNATED and info["iters"] < 50000
     assert info["rel_res_true"] < 1e-12
+
+
+def test_chebyshev_preconditioner_closed_form_on_eigenvectors():
+    # for A v = lam D v the steps from z = 0 on A z = A v leave the error
+    # R_k(lam) v with R_k(t) = T_k((theta - t)/delta) / T_k(theta/delta), so
+    # z = (1 - R_k(lam)) v; T_k evaluated by numpy's Chebyshev series
+    import scipy.linalg as sla
+    from numpy.polynomial import chebyshev as C
+
+    A, _ = system(npts=8)
+    M = A.toarray()
+    d = np.diag(M)
+    lam, V = sla.eigh(M, np.diag(d))
+    assert lam.max() <= 2.0 + 1e-12 and lam.min() > 0  # the Gershgorin bound used
+    a, bnd = pcg.chebyshev_interval()
+    theta, delta = 0.5 * (bnd + a), 0.5 * (bnd - a)
+    for k in (2, 3, 5, 8):
+        Tk = C.Chebyshev.basis(k)
+        for i in (0, 1, len(lam) // 2, len(lam) - 1):
+            v = V[:, i]
+            z = pcg.chebyshev_apply(A, 1.0 / d, M @ v, k)
+            R = Tk((theta - lam[i]) / delta) / Tk(theta / delta)
+            np.testing.assert_allclose(z, (1.0 - R) * v, rtol=0, atol=1e-10 * np.abs(v).max())
+
+
+def test_chebyshev_preconditioner_is_spd_and_cg_converges_faster():
+    A, b = system(npts=10)
+    n = A.shape[0]
+    dinv = 1.0 / A.diagonal()
+    Minv = np.column_stack([pcg.chebyshev_apply(A, dinv, e, 4) for e in np.eye(n)])
+    assert np.abs(Minv - Minv.T).max() <= 1e-12 * np.abs(Minv).max()
+    assert np.linalg.eigvalsh(0.5 * (Minv + Minv.T)).min() > 0
+    A, b = system()
+    xd = pcg.dense_solve(A, b)
+    x1, i1 = pcg.pcg(A, b, tol=1e-10, replace_every=1)
+    for k in (2, 4, 6):
+        xk, ik = pcg.pcg(A, b, tol=1e-10, precond=pcg.CHEBYSHEV, degree=k, replace_every=1)
+        assert ik["status"] == pcg.OK and ik["rel_res_true"] <= 1e-10
+        assert np.linalg.norm(xk - xd) <= 1e-9 * np.linalg.norm(xd)
+        assert ik["iters"] < i1["iters"]
