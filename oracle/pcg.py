@@ -21,6 +21,10 @@ specification the GPU library implements):
         (x_hi, x_lo) += x_acc; x_acc = 0           (group update, double-double)
         stop if ||b - A x_hi||_2 <= tol * ||b||_2  (the float64 vector returned)
         r = b - A (x_hi + x_lo)                   (replacement)
+        restart the direction (p = z) if r.D^{-1}r grew more than 100-fold
+        over the recursive residual it replaces: the recursion had drifted
+        away from the true residual (float32 storage on well-conditioned
+        systems); in float64 the two agree to rounding and this never fires
         stagnation: let k_best be the last check at which the residual fell
         below half the best one seen.  Stop with status STAGNATED once the best
         residual is within 100x of the rounding floor u || |A||x_hi| ||
@@ -167,7 +171,10 @@ def pcg(A, b, tol=1e-10, max_it=100000, replace_every=50, x0=None, record=False,
             if best < 100.0 * floor and k - k_best >= max(stag_checks * replace_every, k_best):
                 info.update(iters=k, rel_res_true=res, status=STAGNATED)
                 return x, info
+            nu_rec = float(r @ (dinv * r))
             r = true_residual(A, b, x, x_lo)
+            if float(r @ (dinv * r)) > 100.0 * nu_rec:
+                rho = np.inf  # restart: beta = 0
         z = prec(r)
         rho_new = float(r @ z)
         p = z + (rho_new / rho) * p

@@ -18,6 +18,7 @@ struct SysState {
   double res2;              // last true residual ||b - A x_hi||^2
   double best_res2;         // smallest res2 seen (stagnation test)
   double rho_ring[2];       // r.z of iterations k (slot k & 1), Chebyshev schedule
+  double nu_rec;            // r.D'^{-1}r of the recursive residual at the last flush
   int32_t iter;             // completed iterations
   int32_t iter_base;        // completed iterations at the start of the current chunk
   int32_t max_it;

@@ -226,9 +226,9 @@ __global__ void __launch_bounds__(1024) k_resid(SetArgs<V, W, I> a, int mode, do
       } else {
         a.z[0][i] = zv;
         if (mode == 0) a.p[0][i] = zv;
-        const double zd = (double)zv;
-        acc[1] += d * zd * zd;
       }
+      const double zd = (double)zv;
+      acc[1] += d * zd * zd;
     }
   }
   tile_partial<3>(acc, a.part3 + 4 * (size_t)t);
@@ -237,7 +237,9 @@ __global__ void __launch_bounds__(1024) k_resid(SetArgs<V, W, I> a, int mode, do
 // One block per system after k_resid: the convergence test on the returned
 // vector; the stagnation test (the best residual norm is within 100x of the
 // rounding floor u || |A||x| || and has not halved for max(stag_it, k_best)
-// iterations); the scalars of the next direction.
+// iterations); the scalars of the next direction, which restarts (beta = 0)
+// when r.D'^{-1}r of the true residual exceeds 100 times that of the
+// recursive residual it replaces (the recursion drifted away from it).
 template <typename V, typename W, typename I>
 __global__ void k_sys_check(SetArgs<V, W, I> a, int mode, int cheb) {
   const int s = blockIdx.x;
@@ -246,7 +248,10 @@ __global__ void k_sys_check(SetArgs<V, W, I> a, int mode, int cheb) {
   if (mode == 2 && S.done == 2) return;
   double r[3];
   sum_range<3>(a.part3, a.sys_tile0[s], a.sys_tile0[s + 1], r);
+  double nr[4] = {S.nu_rec, 0.0, 0.0, 0.0};
+  if (cheb && mode == 1) sum_range<4>(a.part[1], a.sys_tile0[s], a.sys_tile0[s + 1], nr);
   if (threadIdx.x != 0) return;
+  const bool restart = r[1] > 100.0 * nr[0];
   S.res2 = r[0];
   if (mode == 2) return;
   if (!isfinite(r[0])) {
@@ -270,9 +275,11 @@ __global__ void k_sys_check(SetArgs<V, W, I> a, int mode, int cheb) {
       S.status = PM_STAGNATED;
       S.done = 1;
     } else {
-      if (!cheb) {  // the Chebyshev direction kernel forms its own beta
-        S.beta = r[1] / S.rho;
+      if (!cheb) {
+        S.beta = restart ? 0.0 : r[1] / S.rho;
         S.rho = r[1];
+      } else if (restart) {  // the Chebyshev direction kernel forms beta from the ring
+        S.rho_ring[S.iter & 1] = INFINITY;
       }
       S.iter_base = S.iter;
     }
@@ -800,6 +807,7 @@ __global__ void __launch_bounds__(1024) k_cheb_update(SetArgs<V, W, I> a, int j,
   }
   const double al = rho / pq;
   const V* __restrict__ p = a.p[k & 1];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
     const double pi = (double)p[i];
     if (FLUSH) {
@@ -808,6 +816,8 @@ __global__ void __launch_bounds__(1024) k_cheb_update(SetArgs<V, W, I> a, int j,
       a.x64[i] = hi;
       a.xlo[i] = lo;
       a.xacc[i] = V(0);
+      const double yr = (double)a.y[i] - al * (double)a.q[0][i];  // recursive residual
+      acc[0] += a.dp[i] * yr * yr;
     } else {
       a.xacc[i] = (V)((double)a.xacc[i] + al * pi);
       const V yv = (V)((double)a.y[i] - al * (double)a.q[0][i]);
@@ -815,6 +825,9 @@ __global__ void __launch_bounds__(1024) k_cheb_update(SetArgs<V, W, I> a, int j,
       a.zc[1][i] = (V)((double)yv * inv_theta);
     }
   }
+  // the flush's partials go to part[1] (free until the next steps): this
+  // kernel's blocks are still reading part[0]
+  if (FLUSH) tile_partial<4>(acc, a.part[1] + 4 * (size_t)t);
   if (first) {
     S.alpha = al;
     S.iter = k;
@@ -935,6 +948,7 @@ __global__ void __launch_bounds__(1024) k_update_flush(SetArgs<V, W, I> a, int s
     S.alpha = al;
     S.beta = be;
     S.rho = rho;
+    S.nu_rec = rn;  // r.D'^{-1}r of the recursive residual after this update
     S.iter = k;
   }
 }
