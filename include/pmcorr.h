@@ -131,7 +131,9 @@ typedef struct {
   int32_t iter_shape;    /* with tile_rows: the iteration schedule, -1 split
                             (update kernel, then product kernel), 1 or 2 the
                             fused kernel with that many rows per thread and
-                            trip (0 = 1); ignored when the tuner decides */
+                            trip (0 = 1), 3 the fused kernel with the tile's
+                            column window staged in LDS (PM_INVALID_ARG if it
+                            does not fit); ignored when the tuner decides */
 } pm_opts;
 
 typedef struct {
@@ -298,7 +300,7 @@ int pm_time_kernel(pm_mesh* mesh, int32_t which, int32_t n_launch, hipStream_t s
 
 /*
  * Launch shape of the last pcg_solve on this mesh: rows per tile, threads per
- * block and the iteration schedule (pm_opts.iter_shape encoding: 1, 2 or -1),
+ * block and the iteration schedule (pm_opts.iter_shape encoding: 1, 2, 3 or -1),
  * as chosen by the tuner or given in pm_opts.  Returns PM_INVALID_ARG before
  * the first solve.
  */

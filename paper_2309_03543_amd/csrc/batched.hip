@@ -145,7 +145,7 @@ int pcg_solve_batched(pm_batch* B, const double* val64, const double* b, double*
   if (opts) o = *opts;
   if (!(o.tol > 0.0) || o.max_it < 0 || o.replace_every < 1 || o.tile_rows < 0 || o.block < 0 ||
       (o.precision != PM_FP64 && o.precision != PM_MIXED) ||
-      o.iter_shape < -1 || o.iter_shape > 2 ||
+      o.iter_shape < -1 || o.iter_shape > 3 ||
       (o.precond != PM_PREC_JACOBI && o.precond != PM_PREC_CHEBYSHEV) ||
       (o.precond == PM_PREC_CHEBYSHEV && (o.cheb_degree < 2 || o.cheb_degree > 16))) {
     set_error(PM_INVALID_ARG, "pcg_solve_batched: invalid options");

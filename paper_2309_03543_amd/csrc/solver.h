@@ -44,6 +44,10 @@ struct SolveSet {
   // work tiles (rows of one system each), rebuilt when the tile size changes
   int tile_rows = 0, n_tiles = 0, max_tiles = 0;
   int *tile_sys = nullptr, *tile_r0 = nullptr, *tile_r1 = nullptr, *sys_tile0 = nullptr;
+  // columns reached by each tile's rows, [tile_lo, tile_hi], and the widest
+  int *tile_lo = nullptr, *tile_hi = nullptr;
+  int win_max = 0;
+  int lds_limit = 0;  // bytes of LDS one block may use (queried once)
   // workspace: difference-form rows, vectors, partials, states
   void *c = nullptr, *w = nullptr, *idx = nullptr;
   double *dp = nullptr, *x64 = nullptr, *xlo = nullptr, *b64 = nullptr;

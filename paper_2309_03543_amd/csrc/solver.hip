@@ -50,6 +50,8 @@ struct SetArgs {
   const int* tile_r0;
   const int* tile_r1;
   const int* sys_tile0;
+  const int* tile_lo;  // first and last column any row of the tile reaches
+  const int* tile_hi;
   const int* perm;
   const int* rp;
   const int* col;
@@ -618,6 +620,144 @@ __global__ void __launch_bounds__(512) k_iter(SetArgs<V, W, I> a, int src, int j
   }
 }
 
+// LDS-staged fused iteration: the same arithmetic as k_iter, bit for bit.
+// The new z and p of every row in the tile's column window [tile_lo,
+// tile_hi] are formed once, by one thread, into LDS (rows of the tile also
+// store them to global memory there), so the product reads its neighbours
+// from LDS instead of gathering three vectors per neighbour from L2.  Every
+// global load is coalesced and independent of the others: the first
+// staging rows, the first product rows and the partials are all in flight
+// before the reduction waits on any of them.
+template <typename V, typename W, typename I>
+__global__ void __launch_bounds__(512) k_iter_lds(SetArgs<V, W, I> a, int src, int j,
+                                                  double scale) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const int t = xcd_block(blockIdx.x, gridDim.x);
+  const int s = a.tile_sys[t];
+  SysState& S = a.ss[s];
+  if (S.done) return;
+  const int r0 = a.tile_r0[t], r1 = a.tile_r1[t];
+  const int lo = a.tile_lo[t], nwin = a.tile_hi[t] - lo + 1;
+  const int t0 = a.sys_tile0[s], t1 = a.sys_tile0[s + 1];
+  const int B = blockDim.x, tid = threadIdx.x;
+  const size_t N = (size_t)a.N;
+  V* __restrict__ lp = reinterpret_cast<V*>(lds_raw);
+  V* __restrict__ lz = lp + nwin;
+  const V* __restrict__ ps = a.p[src];
+  const V* __restrict__ zs = a.z[src];
+  const V* __restrict__ qs = a.q[src];
+  V* __restrict__ pd = a.p[src ^ 1];
+  V* __restrict__ zd = a.z[src ^ 1];
+  V* __restrict__ qd = a.q[src ^ 1];
+  V* __restrict__ xacc = a.xacc;
+
+  constexpr int kStage = 4;  // staging rows per thread loaded before the reduction
+  V sp[kStage], sz[kStage], sq[kStage];
+#pragma unroll
+  for (int u = 0; u < kStage; ++u) {
+    const int w = tid + u * B;
+    const int i = lo + (w < nwin ? w : nwin - 1);
+    sp[u] = ps[i];
+    sz[u] = zs[i];
+    sq[u] = qs[i];
+  }
+  PartRegs P;
+  partial_load(a.part[src], t0, t1, P);
+  constexpr int R = kUnroll;
+  W w0[R], w1[R], w2[R], cc[R];
+  I i0[R], i1[R], i2[R];
+  V xv[R], pv[R];
+  auto load_rows = [&](int b0) {
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int ir = b0 + u * B;
+      const int i = ir < r1 ? ir : r0;
+      w0[u] = a.w[i];
+      w1[u] = a.w[N + i];
+      w2[u] = a.w[2 * N + i];
+      i0[u] = a.idx[i];
+      i1[u] = a.idx[N + i];
+      i2[u] = a.idx[2 * N + i];
+      cc[u] = a.c[i];
+      xv[u] = xacc[i];
+      pv[u] = ps[i];
+    }
+  };
+  int base = r0 + tid;
+  load_rows(base);
+  double r[4];
+  partial_reduce(a.part[src], t0, t1, P, r);
+
+  const bool first = t == t0 && tid == 0;
+  const int k = S.iter_base + j;
+  const double pq = r[0], rho = r[3];
+  if (const int stop = stop_code(k, S.max_it, pq, rho)) {
+    if (first) {
+      S.status = stop == 100 ? PM_OK : stop;
+      S.done = 1;
+    }
+    return;
+  }
+  const double al = rho / pq;
+  const double rn = rho - 2.0 * al * r[1] + al * al * r[2];
+  const double be = rn / rho;
+  const double as = al * scale, bs = be * scale;
+
+  auto stage = [&](int w, V pold, V zold, V qold) {
+    const V zn = (V)((double)zold - as * (double)qold);
+    const V pn = (V)((double)zn + bs * (double)pold);
+    lp[w] = pn;
+    lz[w] = zn;
+    const int i = lo + w;
+    if (i >= r0 && i < r1) {
+      zd[i] = zn;
+      pd[i] = pn;
+    }
+  };
+#pragma unroll
+  for (int u = 0; u < kStage; ++u) {
+    const int w = tid + u * B;
+    if (w < nwin) stage(w, sp[u], sz[u], sq[u]);
+  }
+  for (int w = tid + kStage * B; w < nwin; w += B) stage(w, ps[lo + w], zs[lo + w], qs[lo + w]);
+  __syncthreads();
+
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (;;) {
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int i = base + u * B;
+      if (i >= r1) continue;
+      xacc[i] = (V)((double)xv[u] + as * (double)pv[u]);
+      const int li = i - lo;
+      const double pi = (double)lp[li], zi = (double)lz[li], ci = (double)cc[u];
+      double y = ci * pi;
+      y += (double)w0[u] * (pi - (double)lp[col_of<I>(i, i0[u]) - lo]);
+      y += (double)w1[u] * (pi - (double)lp[col_of<I>(i, i1[u]) - lo]);
+      y += (double)w2[u] * (pi - (double)lp[col_of<I>(i, i2[u]) - lo]);
+      const double d = ((ci + (double)w0[u]) + (double)w1[u]) + (double)w2[u];
+      const V qn = (V)(y / d);
+      qd[i] = qn;
+      const double qq = (double)qn;
+      const double dq = d * qq;
+      acc[0] += pi * dq;
+      acc[1] += zi * dq;
+      acc[2] += qq * dq;
+      acc[3] += d * zi * zi;
+    }
+    base += R * B;
+    if (base >= r1) break;
+    load_rows(base);
+  }
+  tile_partial<4>(acc, a.part[src ^ 1] + 4 * (size_t)t);
+  if (first) {
+    S.alpha = al;
+    S.beta = be;
+    S.rho = rho;
+    S.iter = k;
+  }
+}
+
 // Split schedule (the tuner may prefer it where the fused kernel's extra
 // neighbour gathers cost more than the pass it saves): after k_spmv on buffer
 // 0, iteration k = iter_base + j updates x_acc, z and p in place with the
@@ -1016,6 +1156,38 @@ int salloc(SolveSet& S, T** ptr, size_t count) {
   return PM_OK;
 }
 
+// Column window of every tile: min and max column over its rows (the CSR
+// holds the diagonal, so the rows themselves are inside).
+__global__ void k_tile_window(const int* tile_r0, const int* tile_r1, const int* rp,
+                              const int* col, int* lo, int* hi) {
+  __shared__ int smn[16], smx[16];
+  const int t = blockIdx.x;
+  int mn = INT_MAX, mx = -1;
+  for (int i = tile_r0[t] + threadIdx.x; i < tile_r1[t]; i += blockDim.x)
+    for (int k = rp[i]; k < rp[i + 1]; ++k) {
+      mn = min(mn, col[k]);
+      mx = max(mx, col[k]);
+    }
+  for (int off = 32; off > 0; off >>= 1) {
+    mn = min(mn, __shfl_xor(mn, off, 64));
+    mx = max(mx, __shfl_xor(mx, off, 64));
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  if (lane == 0) {
+    smn[wid] = mn;
+    smx[wid] = mx;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < nw; ++w) {
+      mn = min(mn, smn[w]);
+      mx = max(mx, smx[w]);
+    }
+    lo[t] = mn;
+    hi[t] = mx;
+  }
+}
+
 int build_tiles(SolveSet& S, int tile_rows) {
   if (S.tile_rows == tile_rows) return PM_OK;
   std::vector<int> ts, t0, t1, st0(S.n_sys + 1);
@@ -1036,8 +1208,16 @@ int build_tiles(SolveSet& S, int tile_rows) {
   PS_HIP(hipMemcpy(S.tile_r0, t0.data(), 4 * t0.size(), hipMemcpyHostToDevice));
   PS_HIP(hipMemcpy(S.tile_r1, t1.data(), 4 * t1.size(), hipMemcpyHostToDevice));
   PS_HIP(hipMemcpy(S.sys_tile0, st0.data(), 4 * st0.size(), hipMemcpyHostToDevice));
+  const int nt = (int)ts.size();
+  k_tile_window<<<nt, 256>>>(S.tile_r0, S.tile_r1, S.rp, S.col, S.tile_lo, S.tile_hi);
+  PS_HIP(hipGetLastError());
+  std::vector<int> lo(nt), hi(nt);
+  PS_HIP(hipMemcpy(lo.data(), S.tile_lo, 4 * (size_t)nt, hipMemcpyDeviceToHost));
+  PS_HIP(hipMemcpy(hi.data(), S.tile_hi, 4 * (size_t)nt, hipMemcpyDeviceToHost));
+  S.win_max = 0;
+  for (int k = 0; k < nt; ++k) S.win_max = std::max(S.win_max, hi[k] - lo[k] + 1);
   S.tile_rows = tile_rows;
-  S.n_tiles = (int)ts.size();
+  S.n_tiles = nt;
   return PM_OK;
 }
 
@@ -1050,6 +1230,8 @@ SetArgs<V, W, I> make_args(SolveSet& S, const double* val, const double* b, doub
   a.tile_r0 = S.tile_r0;
   a.tile_r1 = S.tile_r1;
   a.sys_tile0 = S.sys_tile0;
+  a.tile_lo = S.tile_lo;
+  a.tile_hi = S.tile_hi;
   a.perm = S.perm;
   a.rp = S.rp;
   a.col = S.col;
@@ -1140,6 +1322,8 @@ struct Ops {
       spmv(S, a, L, s);
     } else if (L.rows == 1) {
       k_iter<V, W, I, 1><<<S.n_tiles, L.block, 0, s>>>(a, src, j, scale);
+    } else if (L.rows == 3) {
+      k_iter_lds<V, W, I><<<S.n_tiles, L.block, lds_bytes(S), s>>>(a, src, j, scale);
     } else {
       k_iter<V, W, I, 2><<<S.n_tiles, L.block, 0, s>>>(a, src, j, scale);
     }
@@ -1147,6 +1331,20 @@ struct Ops {
   // m iterations: product on buffer 0, m - 1 iterations (fused: alternating
   // the buffers), the flushing m-th update, the replacement and the new
   // direction (back in buffer 0).
+  static size_t lds_bytes(const SolveSet& S) { return 2 * sizeof(V) * (size_t)S.win_max; }
+  // whether the LDS-staged kernel fits the current tiles, raising the kernel's
+  // dynamic LDS limit when more than the default is needed
+  static bool lds_fits(const SolveSet& S) {
+    const size_t need = lds_bytes(S);
+    if (need > (size_t)S.lds_limit) return false;
+    if (need > 65536 &&
+        hipFuncSetAttribute((const void*)k_iter_lds<V, W, I>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)need) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    return true;
+  }
   static void chunk(SolveSet& S, const A& a, int m, const Launch& L, hipStream_t s) {
     spmv(S, a, L, s);
     int src = 0;
@@ -1204,6 +1402,7 @@ struct Ops {
 constexpr Launch kCandidates[] = {
     {1024, 256, 1}, {2048, 256, 1}, {2048, 512, 1}, {4096, 512, 1}, {2048, 256, 2},
     {4096, 512, 2}, {8192, 512, 2}, {2048, 256, 0}, {4096, 256, 0}, {4096, 512, 0},
+    {1024, 256, 3}, {2048, 256, 3}, {2048, 512, 3}, {4096, 512, 3}, {8192, 512, 3},
 };
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int, int>, Launch> g_tuned;
@@ -1227,18 +1426,24 @@ int tune_launch(SolveSet& S, const double* val64, const double* b, double* x, co
   for (const Launch& L : kCandidates) {
     if ((long)L.tile * 2 > (long)S.N && L.tile != kCandidates[0].tile) continue;
     if (int r = build_tiles(S, L.tile)) return r;
+    if (L.rows == 3 && !Ops<V, W, I>::lds_fits(S)) continue;
     const auto a = make_args<V, W, I>(S, val64, b, x);
     Ops<V, W, I>::start(S, a, ot, L, s);
     Ops<V, W, I>::spmv(S, a, L, s);
     for (int w = 0; w < 4; ++w)  // warm caches and clocks
       Ops<V, W, I>::iter(S, a, w & 1, 1, L, s, 0.0);
-    PS_HIP(hipEventRecord(S.tev[0], s));
-    const int reps = 20;
-    for (int w = 0; w < reps; ++w) Ops<V, W, I>::iter(S, a, w & 1, 1, L, s, 0.0);
-    PS_HIP(hipEventRecord(S.tev[1], s));
-    PS_HIP(hipEventSynchronize(S.tev[1]));
-    float ms = 0.f;
-    PS_HIP(hipEventElapsedTime(&ms, S.tev[0], S.tev[1]));
+    // best of three rounds of ten iterations: single rounds vary by a few
+    // per cent, as much as neighbouring shapes differ
+    float ms = 1e30f;
+    for (int round = 0; round < 3; ++round) {
+      PS_HIP(hipEventRecord(S.tev[0], s));
+      for (int w = 0; w < 10; ++w) Ops<V, W, I>::iter(S, a, w & 1, 1, L, s, 0.0);
+      PS_HIP(hipEventRecord(S.tev[1], s));
+      PS_HIP(hipEventSynchronize(S.tev[1]));
+      float r = 0.f;
+      PS_HIP(hipEventElapsedTime(&r, S.tev[0], S.tev[1]));
+      ms = std::min(ms, r);
+    }
     if (ms < best) {
       best = ms;
       arg = L;
@@ -1258,10 +1463,15 @@ int run(SolveSet& S, const double* val64, const double* b, double* x, const pm_o
   if (o.tile_rows > 0) {
     const int block = o.block > 0 ? std::min(512, std::max(64, (o.block / 64) * 64)) : 256;
     L = {std::max(kMinTile, o.tile_rows), block, o.iter_shape < 0 ? 0 : std::max(1, o.iter_shape)};
+    if (o.precond == PM_PREC_CHEBYSHEV) L.rows = 1;  // the schedule applies to Jacobi only
   } else {
     if (int r = tune_launch<V, W, I>(S, val64, b, x, o, s, &L)) return r;
   }
   if (int r = build_tiles(S, L.tile)) return r;
+  if (L.rows == 3 && !O::lds_fits(S)) {
+    set_error(PM_INVALID_ARG, "the tile's column window does not fit the LDS of one block");
+    return PM_INVALID_ARG;
+  }
   const auto a = make_args<V, W, I>(S, val64, b, x);
   S.last_prec = o.precision;
   S.last_tile = L.tile;
@@ -1364,8 +1574,15 @@ int set_init(SolveSet& S, const std::vector<int>& rows, int64_t nnz, int index_b
   const size_t N = S.N, T = S.max_tiles;
   int r;
   if ((r = salloc(S, &S.tile_sys, T)) || (r = salloc(S, &S.tile_r0, T)) ||
-      (r = salloc(S, &S.tile_r1, T)) || (r = salloc(S, &S.sys_tile0, S.n_sys + 1)))
+      (r = salloc(S, &S.tile_r1, T)) || (r = salloc(S, &S.sys_tile0, S.n_sys + 1)) ||
+      (r = salloc(S, &S.tile_lo, T)) || (r = salloc(S, &S.tile_hi, T)))
     return r;
+  {
+    int dev = 0, lim = 0;
+    PS_HIP(hipGetDevice(&dev));
+    PS_HIP(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    S.lds_limit = lim;
+  }
   double* d;
   int32_t* i32;
   if ((r = salloc(S, &d, N))) return r;

@@ -93,7 +93,7 @@ def test_batched_iteration_limit():
     assert all(i["status"] == B().PM_MAXIT and i["iters"] == 20 for i in infos)
 
 
-@pytest.mark.parametrize("shape", [-1, 1, 2])
+@pytest.mark.parametrize("shape", [-1, 1, 2, 3])
 def test_batched_schedules_agree(shape):
     # split schedule and fused kernels of several shapes, tiles straddling no
     # system: every system converges to the same solution

@@ -204,7 +204,8 @@ def test_solves_are_deterministic_and_launch_shape_independent():
     for prec in (0, 1):
         xr, ir = B().pcg_solve(c["mesh"], val, b, precision=prec)
         for tile, block, shape in ((256, 256, 1), (768, 64, 2), (4096, 512, 1), (1024, 256, -1),
-                                   (512, 128, -1), (2048, 256, 2), (1024, 192, 1)):
+                                   (512, 128, -1), (2048, 256, 2), (1024, 192, 1), (1024, 256, 3),
+                                   (2048, 512, 3), (300, 64, 3)):
             x3, i3 = B().pcg_solve(c["mesh"], val, b, precision=prec, tile_rows=tile, block=block,
                                    iter_shape=shape)
             assert i3["status"] == 0
@@ -214,6 +215,20 @@ def test_solves_are_deterministic_and_launch_shape_independent():
             x4, i4 = B().pcg_solve(c["mesh"], val, b, precision=prec, tile_rows=tile, block=block,
                                    iter_shape=shape)
             assert torch.equal(x3, x4) and i3["iters"] == i4["iters"]
+
+
+def test_lds_staged_iteration_is_bitwise_the_gather_one():
+    c = case("chan")
+    w = c["w"]
+    val = B().assemble_corrector(c["mesh"], B().PM_CP2, c["prm"], w["nu"], w["dt"])["val64"]
+    b = torch.tensor(w["rhs"]["cp2"], device=c["dev"])
+    for prec in (0, 1):
+        for tile, block in ((1024, 256), (2048, 512)):
+            x1, i1 = B().pcg_solve(c["mesh"], val, b, precision=prec, tile_rows=tile, block=block,
+                                   iter_shape=1)
+            x3, i3 = B().pcg_solve(c["mesh"], val, b, precision=prec, tile_rows=tile, block=block,
+                                   iter_shape=3)
+            assert i1["status"] == 0 and torch.equal(x1, x3) and i1["iters"] == i3["iters"]
 
 
 def test_error_statuses():
