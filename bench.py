@@ -195,6 +195,23 @@ def main():
     wall64, inf64 = timed(0)
     solves_per_step = len(inf64[-1])
     value = solves_per_step * args.steps / wall64
+    # solve alone (assembly excluded): median of repeated float64 solves of
+    # the step's last system, timed with HIP events on the current stream
+    solve_only = None
+    if batch is None and wl != "adjoint":
+        key, kind = kinds[-1]
+        val = B.assemble_corrector(mesh0, kind, prm0, w0["nu"], w0["dt"])["val64"]
+        times = []
+        for _ in range(10):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            _, info = B.pcg_solve(mesh0, val, rhs[0][key])
+            e1.record()
+            e1.synchronize()
+            times.append(e0.elapsed_time(e1))
+        med = float(np.median(times))
+        solve_only = {"system": key, "ms_median": med, "solves_per_s": 1e3 / med,
+                      "iters": info["iters"], "reps": len(times)}
     # per-kernel timing on the state of the last solve of the step
     tmesh = mesh0 if batch is None else None
     kern = {}
@@ -314,6 +331,7 @@ def main():
                    "iters": iter_summary(inf64[-1])},
         "roofline": roof,
         "kernels": kern,
+        "solve_only": solve_only,
         "mixed": mixed,
         "sequential": sequential,
         "cpu_baseline": cpu,
