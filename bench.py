@@ -102,6 +102,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--solve-reps", type=int, default=10,
+                    help="repeated float64 solves for the solve-only median (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after timing, run a plain device copy of 256 MiB five times, whose "
                          "known traffic calibrates the FETCH_SIZE / WRITE_SIZE counters")
@@ -198,11 +200,11 @@ def main():
     # solve alone (assembly excluded): median of repeated float64 solves of
     # the step's last system, timed with HIP events on the current stream
     solve_only = None
-    if batch is None and wl != "adjoint":
+    if batch is None and wl != "adjoint" and args.solve_reps > 0:
         key, kind = kinds[-1]
         val = B.assemble_corrector(mesh0, kind, prm0, w0["nu"], w0["dt"])["val64"]
         times = []
-        for _ in range(10):
+        for _ in range(args.solve_reps):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
             _, info = B.pcg_solve(mesh0, val, rhs[0][key])

@@ -47,36 +47,6 @@ __device__ __forceinline__ void block_partial(double (&v)[NV], double* part) {
   }
 }
 
-// Fixed-order sum of the NV-component partials of nb blocks (stride NV).
-// Every thread of the calling block receives the same result, so all blocks
-// of a kernel that call it agree bit for bit.
-template <int NV>
-__device__ __forceinline__ void sum_partials(const double* __restrict__ part, int nb,
-                                             double (&out)[NV]) {
-  __shared__ double sh[NV][16];
-  __shared__ double res[NV];
-  double v[NV];
-#pragma unroll
-  for (int k = 0; k < NV; ++k) v[k] = 0.0;
-  for (int b = threadIdx.x; b < nb; b += blockDim.x)
-#pragma unroll
-    for (int k = 0; k < NV; ++k) v[k] += part[(size_t)b * NV + k];
-  wave_sum<NV>(v);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
-  if (lane == 0)
-#pragma unroll
-    for (int k = 0; k < NV; ++k) sh[k][wid] = v[k];
-  __syncthreads();
-  if (threadIdx.x < NV) {
-    double s = 0.0;
-    for (int w = 0; w < nw; ++w) s += sh[threadIdx.x][w];
-    res[threadIdx.x] = s;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < NV; ++k) out[k] = res[k];
-}
-
 template <typename I>
 __device__ __forceinline__ int col_of(int i, I v);
 template <>

@@ -214,12 +214,68 @@ __global__ void __launch_bounds__(1024) k_resid(SetArgs<V, W, I> a, int mode, do
   const int s = a.tile_sys[t];
   if (mode != 2 && a.ss[s].done) return;
   double acc[3] = {0.0, 0.0, 0.0};
-  for (int i = a.tile_r0[t] + threadIdx.x; i < a.tile_r1[t]; i += blockDim.x) {
-    double rh, rd, ax;
-    residual_row(a.b64[i], a.val, a.col, a.x64, a.xlo, a.rp[i], a.rp[i + 1], rh, rd, ax);
-    acc[0] += rh * rh;
-    acc[2] += ax * ax;
-    if (mode != 2) {
+  // Rows of these meshes hold at most kRowMax entries (three neighbours and
+  // the diagonal); every load of R rows is issued before the first use, and
+  // the compensated sums run over the entries in CSR order with zero padding
+  // (exact no-ops), the same arithmetic as residual_row.  Longer rows finish
+  // in residual_row's loop.
+  constexpr int R = 2, kRowMax = 4;
+  const int r0 = a.tile_r0[t], r1 = a.tile_r1[t];
+  for (int base = r0 + threadIdx.x; base < r1; base += R * blockDim.x) {
+    int k0[R], k1[R], cj[R][kRowMax];
+    double bi[R], av[R][kRowMax], xh[R][kRowMax], xl[R][kRowMax];
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int i = base + u * (int)blockDim.x;
+      const int ii = i < r1 ? i : r0;
+      k0[u] = a.rp[ii];
+      k1[u] = a.rp[ii + 1];
+      bi[u] = a.b64[ii];
+    }
+#pragma unroll
+    for (int u = 0; u < R; ++u)
+#pragma unroll
+      for (int e = 0; e < kRowMax; ++e) {
+        const int k = k0[u] + e < k1[u] ? k0[u] + e : k0[u];
+        cj[u][e] = a.col[k];
+        av[u][e] = k0[u] + e < k1[u] ? a.val[k] : 0.0;
+      }
+#pragma unroll
+    for (int u = 0; u < R; ++u)
+#pragma unroll
+      for (int e = 0; e < kRowMax; ++e) {
+        xh[u][e] = a.x64[cj[u][e]];
+        xl[u][e] = a.xlo[cj[u][e]];
+      }
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int i = base + u * (int)blockDim.x;
+      if (i >= r1) continue;
+      double sum = bi[u], e = 0.0, el = 0.0, m = 0.0;
+#pragma unroll
+      for (int q = 0; q < kRowMax; ++q) {
+        const double av_ = av[u][q], xv = xh[u][q];
+        const double pr = av_ * xv;
+        m += fabs(pr);
+        const double pe = __builtin_fma(av_, xv, -pr);
+        const double tt = sum - pr;
+        const double bb = tt - sum;
+        const double err = (sum - (tt - bb)) + (-pr - bb);
+        sum = tt;
+        e += err - pe;
+        el -= av_ * xl[u][q];
+      }
+      double rh = sum + e, rd = sum + (e + el), ax = m;
+      if (k1[u] - k0[u] > kRowMax) {  // not on triangle meshes; kept general
+        double rh2, rd2, ax2;
+        residual_row(0.0, a.val, a.col, a.x64, a.xlo, k0[u] + kRowMax, k1[u], rh2, rd2, ax2);
+        rh += rh2;
+        rd += rd2;
+        ax += ax2;
+      }
+      acc[0] += rh * rh;
+      acc[2] += ax * ax;
+      if (mode == 2) continue;
       const double d = a.dp[i];
       const V zv = (V)(rd / d);
       if (inv_theta > 0.0) {
@@ -305,7 +361,6 @@ __global__ void __launch_bounds__(1024) k_pdir(SetArgs<V, W, I> a, int src) {
 // Rows handled per thread and loop trip: every load of the group is issued
 // before the first use, so each thread keeps R rows of memory traffic in flight.
 constexpr int kUnroll = 4;
-constexpr int kUnrollIter = 2;
 
 // Stop decision of an update from the reduced product partials (identical in
 // every block of the system): 0 = go on, 100 = exact zero residual, else the
