@@ -72,25 +72,28 @@ def source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, algorithmic_bytes: float):
-    """HBM bytes per launch of the dominant kernel from the stored counter
-    summary (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), or None when
-    there is none for this workload or the kernels changed since."""
+def measured_traffic(workload: str, launch: dict, kernel: str):
+    """HBM bytes per launch of the dominant kernel, for this launch shape, from
+    the stored counter summary (FETCH_SIZE + WRITE_SIZE calibrated on a plain
+    copy), or None when the summary lacks this shape or the kernels changed
+    since it was taken."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.txt")
     if not os.path.exists(path):
         return None
-    kv = {}
+    digest, found = None, None
     with open(path) as fh:
         for line in fh:
-            if ":" in line and not line.startswith("#"):
-                k, v = line.split(":", 1)
-                kv[k.strip()] = v.strip()
-    if kv.get("source_digest") != source_digest():
+            if line.startswith("source_digest:"):
+                digest = line.split(":", 1)[1].strip()
+            elif line.startswith("shape:"):
+                f = line.split(":", 1)[1].split()
+                # shape: <kernel> <iter_shape> <tile_rows> <block> <bytes per launch> ...
+                if (f[0] == kernel and int(f[1]) == launch["iter_shape"]
+                        and int(f[2]) == launch["tile_rows"] and int(f[3]) == launch["block"]):
+                    found = float(f[4])
+    if digest != source_digest():
         return None
-    try:
-        return float(kv["traffic_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+    return found
 
 
 def main():
@@ -233,7 +236,7 @@ def main():
         achieved = kern[dom]["GBs"]
         roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                "traffic": measured_traffic(wname, kern[dom]["bytes"]),
+                "traffic": measured_traffic(wname, launch, dom),
                 "ms_per_launch": kern[dom]["ms"], "bytes_per_launch": kern[dom]["bytes"],
                 "launches_per_solve": it_last}
     else:
