@@ -9,7 +9,9 @@
  * triangle (Sec. 3.2.2, eq. CS1_sys_coeff; Sec. 3.2.3, eq. CS2_sys_coeff).
  * This library builds their sparsity once per mesh, assembles their values
  * from per-cell porosity and permeability on the GPU, and solves them with
- * Jacobi-preconditioned conjugate gradients on the GPU.
+ * Jacobi- or Chebyshev-polynomial-preconditioned conjugate gradients on the
+ * GPU (single systems or batches of systems of uneven size), with a
+ * hand-written adjoint for gradients with respect to the cell parameters.
  *
  * Conventions shared by every entry point
  *   - Triangles are given counter-clockwise; side j of triangle e is the side

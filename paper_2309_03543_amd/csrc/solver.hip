@@ -1487,12 +1487,12 @@ int tune_launch(SolveSet& S, const double* val64, const double* b, double* x, co
     Ops<V, W, I>::spmv(S, a, L, s);
     for (int w = 0; w < 4; ++w)  // warm caches and clocks
       Ops<V, W, I>::iter(S, a, w & 1, 1, L, s, 0.0);
-    // best of three rounds of ten iterations: single rounds vary by a few
+    // best of three rounds of twenty iterations: single rounds vary by a few
     // per cent, as much as neighbouring shapes differ
     float ms = 1e30f;
     for (int round = 0; round < 3; ++round) {
       PS_HIP(hipEventRecord(S.tev[0], s));
-      for (int w = 0; w < 10; ++w) Ops<V, W, I>::iter(S, a, w & 1, 1, L, s, 0.0);
+      for (int w = 0; w < 20; ++w) Ops<V, W, I>::iter(S, a, w & 1, 1, L, s, 0.0);
       PS_HIP(hipEventRecord(S.tev[1], s));
       PS_HIP(hipEventSynchronize(S.tev[1]));
       float r = 0.f;
