@@ -18,6 +18,9 @@ Modules
              replacement; dense Cholesky reference (Sec. 3.2.2-3.2.3)
   adjoint    adjoint solve and parameter gradients (derived from the
              symmetric corrector systems)
+  crossflux  co-normal tangential flux terms of the CP2 and the right-hand
+             side B_2 of its second solve (Sec. 3.2.3, eq. Cs2_7,
+             eq. eta_flux; App. C, eq. A3.1-A3.2)
 
 Parity status: every function above is pinned by tests/test_oracle_*.py
 against closed forms, invariants, special cases or brute force; none is
