@@ -12,7 +12,9 @@ Workloads (--workload)
   channel        4x1 channel with a porous block, ~1.0M triangles refined 4x
                  near the block, isotropic K; CP1x and CP2 per step (default)
   channel_aniso  the same recipe at ~4.0M triangles with anisotropic K (ratio
-                 100 rotated 30 deg); CP2 per step
+                 100 rotated 30 deg); CP2 per step; also reports the two-solve
+                 CP2 sequence (cross terms of the first solution on the second
+                 right-hand side) and its cross-term kernels
   square         unit square 64x64 jittered grid (~8k triangles); CP2
   batch          64 unit squares of 50k-500k triangles with log-normal K;
                  one batched CP2 solve per step
@@ -242,6 +244,31 @@ def main():
     else:
         roof = None
 
+    two_step = None
+    if wl == "channel_aniso":
+        # the CP2 sequence of two solves with the cross terms of the first
+        # solution on the second right-hand side, and the cross-term kernels
+        log("timing the two-solve CP2 sequence")
+        val = B.assemble_corrector(mesh0, B.PM_CP2, prm0, w0["nu"], w0["dt"])["val64"]
+        b = rhs[0]["cp2"]
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        eta, eta_t, infs = B.cp2_solve_two_step(mesh0, val, prm0, w0["nu"], w0["dt"], b)
+        torch.cuda.synchronize()
+        wall2 = time.perf_counter() - t
+        ms3, by3 = B.pm_time_cross(mesh0, prm0, w0["nu"], w0["dt"], eta_t, b, 50)
+        b2 = B.cp2_cross_rhs(mesh0, prm0, w0["nu"], w0["dt"], eta_t, b)
+        ck = {name: {"ms": ms, "bytes": by, "GBs": by / ms / 1e6,
+                     "frac_hbm": by / ms / 1e6 / HBM_PEAK_GBS}
+              for name, ms, by in zip(("k_cross_prep", "k_cross_est", "k_cross_rhs"), ms3, by3)}
+        two_step = {"ms": wall2 * 1e3, "iters": [i["iters"] for i in infs],
+                    "status": [i["status"] for i in infs],
+                    "rel_res_true": [i["rel_res_true"] for i in infs],
+                    "cross_over_b": float(torch.linalg.norm(b2 - b) / torch.linalg.norm(b)),
+                    "kernels": ck}
+        log(f"  two-step: {two_step['iters']} iterations, {wall2 * 1e3:.1f} ms; cross kernels "
+            + ", ".join(f"{k} {v['ms'] * 1e3:.1f}us {v['GBs']:.0f}GB/s" for k, v in ck.items()))
+
     sequential = None
     if batch is not None:
         # the same systems solved one after another with pcg_solve
@@ -339,6 +366,7 @@ def main():
         "solve_only": solve_only,
         "mixed": mixed,
         "sequential": sequential,
+        "cp2_two_step": two_step,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

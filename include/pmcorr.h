@@ -11,7 +11,9 @@
  * from per-cell porosity and permeability on the GPU, and solves them with
  * Jacobi- or Chebyshev-polynomial-preconditioned conjugate gradients on the
  * GPU (single systems or batches of systems of uneven size), with a
- * hand-written adjoint for gradients with respect to the cell parameters.
+ * hand-written adjoint for gradients with respect to the cell parameters and
+ * the co-normal cross terms that form the right-hand side of the second CP2
+ * solve.
  *
  * Conventions shared by every entry point
  *   - Triangles are given counter-clockwise; side j of triangle e is the side
@@ -278,6 +280,72 @@ int pcg_adjoint(pm_mesh* mesh, int32_t kind, const pm_cell_params* params, doubl
                 const double* g_dirichlet, const double* val64, const double* eta,
                 const double* grad_eta, double* lambda, double* grad_logk, double* grad_eps,
                 const pm_opts* opts, pm_info* info, hipStream_t stream);
+
+/*
+ * Right-hand side of the second CP2 solve (Sec. 3.2.3, eq. Cs2_7 and
+ * eq. eta_flux; App. C, eq. A3.1-A3.2).  On a non-K-orthogonal mesh the flux
+ * of Xi grad(eta) through a side has, beside the two-point normal part of the
+ * matrix, a tangential part d_{j,tau} . grad(eta), d_j = Xi_j n_j.  Each cell
+ * writes d_{j,tau} on the outward normals of its two other sides (co-normal
+ * decomposition) and estimates each normal derivative by the circumcenter
+ * difference quotient used by the matrix; the side's term is half the
+ * difference of the two cells' estimates (each built on its own outward
+ * normal), so it is continuous across the side and exact for linear eta and
+ * constant Xi.  With eta~ the solution of A eta~ = b_in (eq. Cs2_7, first
+ * system) this computes
+ *   b_out = b_in + sum_j l_j T_j(eta~)
+ * and A eta = b_out is the second system.  Boundary sides: a CP2 Dirichlet
+ * side takes its g_dirichlet value in place of a neighbour's eta and carries
+ * its own cell's estimate; an estimate that would need a Neumann side is
+ * dropped (an interior side then takes the other cell's estimate alone);
+ * Neumann sides carry no tangential term.  Isotropic Xi gives b_out = b_in.
+ *   params, nu, dt, g_dirichlet  as given to assemble_corrector for PM_CP2
+ *   eta_tilde  device [n_cells], cell order
+ *   b_in       device [n_cells], cell order: the first system's right-hand side
+ *   b_out      device [n_cells] out, cell order; may equal b_in
+ * Errors: PM_INVALID_ARG, PM_NONFINITE (non-finite parameters or eta_tilde;
+ * checked on the device, reported after a stream sync).  Uses the mesh's
+ * workspace: calls on one mesh must not overlap in time.
+ */
+int cp2_cross_rhs(pm_mesh* mesh, const pm_cell_params* params, double nu, double dt,
+                  const double* g_dirichlet, const double* eta_tilde, const double* b_in,
+                  double* b_out, hipStream_t stream);
+
+/*
+ * The CP2 sequence of eq. Cs2_7 with one matrix: eta~ from A eta~ = b (zero
+ * initial guess), then eta from A eta = cp2_cross_rhs(eta~, b), starting from
+ * eta~.  Both solves use pcg_solve with opts (x0_is_zero is ignored).
+ *   val64            device [nnz], the PM_CP2 matrix of assemble_corrector
+ *   params .. g      as given to assemble_corrector for PM_CP2
+ *   b                device [n_cells], cell order: B_1 plus the Dirichlet lift
+ *   eta_tilde, eta   device [n_cells] out, cell order; distinct from b and
+ *                    from each other
+ *   info             host [2] out, nullable: the two solves
+ * Returns the first negative status, else the first non-OK one, else PM_OK.
+ * The sequence is one step of the fixed-point iteration
+ * eta <- A^{-1}(b + C eta) for the full flux (C: the cross terms); it moves
+ * eta~ towards the full solution when that iteration contracts, which holds
+ * for mild anisotropy of Xi but not for eigenvalue ratios of Xi above about
+ * eight on the meshes tested.
+ */
+int cp2_solve_two_step(pm_mesh* mesh, const double* val64, const pm_cell_params* params, double nu,
+                       double dt, const double* g_dirichlet, const double* b, double* eta_tilde,
+                       double* eta, const pm_opts* opts, pm_info* info, hipStream_t stream);
+
+/*
+ * Measurement hook for cp2_cross_rhs: runs it n_launch times (after one
+ * warm-up) with HIP events around each of its three kernels and returns the
+ * mean durations in ms (ms[3]: per-cell preparation of Xi and eta~, the
+ * estimates, the right-hand side) and the bytes each must move (bytes[3],
+ * nullable), counting every array element once: n (60 + 8 g) with g the
+ * number of the optional chi, g11, g12, g22 given; n (57 + 3 (4 + 1 + 24)) =
+ * 144 n; n (29 + 3 * 6 + 16) = 63 n.  Dirichlet values are not counted.
+ * b_in and b_out must differ here (b_out is overwritten n_launch + 1 times).
+ */
+int pm_time_cross(pm_mesh* mesh, const pm_cell_params* params, double nu, double dt,
+                  const double* g_dirichlet, const double* eta_tilde, const double* b_in,
+                  double* b_out, int32_t n_launch, hipStream_t stream, double* ms,
+                  double* bytes);
 
 /*
  * Measurement hook: runs one of the solver's iteration kernels n_launch times

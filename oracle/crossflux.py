@@ -84,20 +84,25 @@ def conormal_split(geo: dict, Xs: np.ndarray) -> dict:
     """Per (cell e, side j): d_j = Xi_j n_j, d_{j,n} = d_j . n_j,
     d_{j,tau} = d_j - d_{j,n} n_j, and the coefficients c[e, j, a] of
     d_{j,tau} on the outward normals of the other two sides a of e (c is 0
-    for a = j), from the 2x2 system [n_a n_b] (c_a, c_b)^T = d_{j,tau}."""
+    for a = j), from the 2x2 system [n_a n_b] (c_a, c_b)^T = d_{j,tau}.
+    cbound[e, j] = |d_j| ||[n_a n_b]^{-1}||_F bounds |c| for any tangential
+    part up to |d_j|: the size against which rounding in c is measured (c
+    itself cancels to 0 when Xi is isotropic)."""
     nrm, l = unit_normals(geo)
     n = geo["n"]
     d = np.einsum("ejab,ejb->eja", Xs, nrm)
     dn = np.einsum("eja,eja->ej", d, nrm)
     dtau = d - dn[..., None] * nrm
     c = np.zeros((n, 3, 3))
+    cbound = np.zeros((n, 3))
     for j in range(3):
         a, b = (j + 1) % 3, (j + 2) % 3
         Mab = np.stack([nrm[:, a], nrm[:, b]], axis=-1)  # columns n_a, n_b
         cab = np.linalg.solve(Mab, dtau[:, j][..., None])[..., 0]
         c[:, j, a] = cab[:, 0]
         c[:, j, b] = cab[:, 1]
-    return {"d": d, "dn": dn, "dtau": dtau, "c": c, "n": nrm, "l": l}
+        cbound[:, j] = np.linalg.norm(d[:, j], axis=-1) * np.linalg.norm(np.linalg.inv(Mab), axis=(1, 2))
+    return {"d": d, "dn": dn, "dtau": dtau, "c": c, "cbound": cbound, "n": nrm, "l": l}
 
 
 def normal_derivatives(geo: dict, eta, g=None) -> tuple:
@@ -126,14 +131,14 @@ def tangential_estimates(geo: dict, split: dict, eta, g=None) -> dict:
     d_{j,tau} . grad(eta) (App. C, eq. A3.2); avail[e, j] is False when a
     Neumann side would be needed."""
     q, have, qabs = normal_derivatives(geo, eta, g)
-    c = split["c"]
+    c, cb = split["c"], split["cbound"]
     E = np.zeros((geo["n"], 3))
     Eabs = np.zeros((geo["n"], 3))
     avail = np.ones((geo["n"], 3), bool)
     for j in range(3):
         for a in ((j + 1) % 3, (j + 2) % 3):
             E[:, j] += c[:, j, a] * q[:, a]
-            Eabs[:, j] += np.abs(c[:, j, a]) * qabs[:, a]
+            Eabs[:, j] += cb[:, j] * qabs[:, a]
             avail[:, j] &= have[:, a]
     E = np.where(avail, E, 0.0)
     Eabs = np.where(avail, Eabs, 0.0)

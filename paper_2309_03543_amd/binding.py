@@ -90,6 +90,9 @@ def lib():
             "pcg_adjoint": (C.c_int, [P, I32, P, D, D, P, P, P, P, P, P, P, P, P, P]),
             "pm_time_kernel": (C.c_int, [P, I32, I32, P, P, P]),
             "pm_last_launch": (C.c_int, [P, P, P, P]),
+            "cp2_cross_rhs": (C.c_int, [P, P, D, D, P, P, P, P, P]),
+            "pm_time_cross": (C.c_int, [P, P, D, D, P, P, P, P, I32, P, P, P]),
+            "cp2_solve_two_step": (C.c_int, [P, P, P, D, D, P, P, P, P, P, P, P]),
         }
         for name, (res, args) in sig.items():
             if hasattr(L, name):
@@ -312,6 +315,53 @@ def pcg_adjoint(mesh: Mesh, kind, params, nu, dt, val64, eta, grad_eta, g_dirich
     return lam, gs, ge, info.as_dict()
 
 
+def cp2_cross_rhs(mesh: Mesh, params, nu, dt, eta_tilde, b_in, b_out=None, g_dirichlet=None,
+                  stream=None):
+    """b_out = b_in + the CP2 cross terms at eta_tilde (device tensors, cell
+    order); b_out may be b_in.  Returns b_out."""
+    import torch
+
+    if b_out is None:
+        b_out = torch.empty_like(b_in)
+    p, _keep = _params(params)
+    _check(lib().cp2_cross_rhs(mesh.handle, C.addressof(p), nu, dt, _ptr(g_dirichlet),
+                               _ptr(eta_tilde), _ptr(b_in), _ptr(b_out), _stream(stream)))
+    return b_out
+
+
+def cp2_solve_two_step(mesh: Mesh, val64, params, nu, dt, b, g_dirichlet=None, stream=None,
+                       **opts):
+    """The two CP2 solves of one step (eta~, then eta with the cross terms of
+    eta~ on the right-hand side).  Returns (eta, eta_tilde, [info1, info2]);
+    negative statuses raise."""
+    import torch
+
+    eta_t = torch.empty_like(b)
+    eta = torch.empty_like(b)
+    o = make_opts(**opts)
+    infos = (pm_info * 2)()
+    p, _keep = _params(params)
+    _check(lib().cp2_solve_two_step(mesh.handle, _ptr(val64), C.addressof(p), nu, dt,
+                                    _ptr(g_dirichlet), _ptr(b), _ptr(eta_t), _ptr(eta),
+                                    C.addressof(o), infos, _stream(stream)))
+    return eta, eta_t, [i.as_dict() for i in infos]
+
+
+def pm_time_cross(mesh: Mesh, params, nu, dt, eta_tilde, b_in, n_launch: int, g_dirichlet=None,
+                  stream=None):
+    """Mean ms and bytes per launch of the three cross-term kernels."""
+    import torch
+
+    b_out = torch.empty_like(b_in)
+    ms = (C.c_double * 3)()
+    by = (C.c_double * 3)()
+    p, _keep = _params(params)
+    _check(lib().pm_time_cross(mesh.handle, C.addressof(p), nu, dt, _ptr(g_dirichlet),
+                               _ptr(eta_tilde), _ptr(b_in), _ptr(b_out), n_launch, _stream(stream),
+                               ms, by))
+    return list(ms), list(by)
+
+
 def pm_time_kernel(mesh: Mesh, which: int, n_launch: int, stream=None):
     """(ms per launch, bytes per launch) of an iteration kernel of the last solve."""
     ms = C.c_double()
@@ -332,5 +382,6 @@ EXPORTED = [
     "pm_opts_default", "pm_status_string", "pm_last_error", "pm_structure_host", "pm_mesh_create",
     "pm_mesh_destroy", "pm_mesh_get_stats", "pm_mesh_export", "assemble_corrector", "pcg_solve",
     "pm_batch_create", "pm_batch_destroy", "pm_batch_offsets", "pcg_solve_batched", "pcg_adjoint",
-    "pm_time_kernel", "pm_last_launch",
+    "pm_time_kernel", "pm_last_launch", "cp2_cross_rhs", "pm_time_cross",
+    "cp2_solve_two_step",
 ]

@@ -54,8 +54,47 @@ int get_error(char* buf, int32_t len) {
 // Assembly kernels (eq. CS1_sys_coeff, eq. Cs2_4, eq. CS2_sys_coeff)
 // ---------------------------------------------------------------------------
 
-// Per cell, in the renumbered order: Kfrak = chi exp(-s) G, M = I/dt + nu eps Kfrak,
-// S = I + nu eps dt Kfrak, Xi = eps dt S^{-1}.
+// The caller's data of cell o: Kfrak = chi exp(-s) G (its diagonal in K11,
+// K22) and Xi = eps dt S^{-1} with S = I + nu eps dt Kfrak, which is eps M^{-1}
+// for M = I/dt + nu eps Kfrak.  Flags err and returns false for non-finite or
+// invalid data (eps <= 0, chi < 0, G not positive definite).
+__device__ __forceinline__ bool cell_xi(int o, const double* __restrict__ eps,
+                                        const double* __restrict__ logk,
+                                        const double* __restrict__ chi,
+                                        const double* __restrict__ g11,
+                                        const double* __restrict__ g12,
+                                        const double* __restrict__ g22, double nu, double dt,
+                                        double& e, double& K11, double& K22, double& X11,
+                                        double& X12, double& X22, int32_t* err) {
+  e = eps[o];
+  const double s = logk[o];
+  const double ch = chi ? chi[o] : 1.0;
+  const double a11 = g11 ? g11[o] : 1.0, a12 = g12 ? g12[o] : 0.0, a22 = g22 ? g22[o] : 1.0;
+  const bool finite_in = isfinite(e) && isfinite(s) && isfinite(ch) && isfinite(a11) &&
+                         isfinite(a12) && isfinite(a22);
+  if (!finite_in) {
+    atomicExch(err, PM_NONFINITE);
+    return false;
+  }
+  if (!(e > 0.0) || ch < 0.0 || !(a11 * a22 - a12 * a12 > 0.0) || !(a11 > 0.0)) {
+    atomicExch(err, PM_INVALID_ARG);
+    return false;
+  }
+  const double k = ch * exp(-s);
+  K11 = k * a11;
+  K22 = k * a22;
+  const double K12 = k * a12;
+  const double c = nu * e * dt;
+  const double S11 = 1.0 + c * K11, S12 = c * K12, S22 = 1.0 + c * K22;
+  const double det = S11 * S22 - S12 * S12;
+  const double f = e * dt / det;
+  X11 = f * S22;
+  X12 = -f * S12;
+  X22 = f * S11;
+  return true;
+}
+
+// Per cell, in the renumbered order: Xi and the diagonal of M = I/dt + nu eps Kfrak.
 __global__ void k_cell_tensors(int n, const int* __restrict__ perm, const double* __restrict__ eps,
                                const double* __restrict__ logk, const double* __restrict__ chi,
                                const double* __restrict__ g11, const double* __restrict__ g12,
@@ -65,31 +104,14 @@ __global__ void k_cell_tensors(int n, const int* __restrict__ perm, const double
                                double* __restrict__ M22, int32_t* err) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int o = perm[i];
-  const double e = eps[o], s = logk[o];
-  const double ch = chi ? chi[o] : 1.0;
-  const double a11 = g11 ? g11[o] : 1.0, a12 = g12 ? g12[o] : 0.0, a22 = g22 ? g22[o] : 1.0;
-  const bool finite_in = isfinite(e) && isfinite(s) && isfinite(ch) && isfinite(a11) &&
-                         isfinite(a12) && isfinite(a22);
-  if (!finite_in) {
-    atomicExch(err, PM_NONFINITE);
+  double e, K11, K22, x11, x12, x22;
+  if (!cell_xi(perm[i], eps, logk, chi, g11, g12, g22, nu, dt, e, K11, K22, x11, x12, x22, err))
     return;
-  }
-  if (!(e > 0.0) || ch < 0.0 || !(a11 * a22 - a12 * a12 > 0.0) || !(a11 > 0.0)) {
-    atomicExch(err, PM_INVALID_ARG);
-    return;
-  }
-  const double k = ch * exp(-s);
-  const double K11 = k * a11, K12 = k * a12, K22 = k * a22;
   M11[i] = 1.0 / dt + nu * e * K11;
   M22[i] = 1.0 / dt + nu * e * K22;
-  const double c = nu * e * dt;
-  const double S11 = 1.0 + c * K11, S12 = c * K12, S22 = 1.0 + c * K22;
-  const double det = S11 * S22 - S12 * S12;
-  const double f = e * dt / det;
-  X11[i] = f * S22;
-  X12[i] = -f * S12;
-  X22[i] = f * S11;
+  X11[i] = x11;
+  X12[i] = x12;
+  X22[i] = x22;
 }
 
 // n.A.n for the outward unit normal of the CCW side vector t.
@@ -215,6 +237,130 @@ __global__ void k_adjoint_grad(int n, int kind, const int* __restrict__ perm,
   grad_e[old] = ge;
 }
 
+// ---------------------------------------------------------------------------
+// CP2 cross terms: right-hand side of the second CP2 solve (Sec. 3.2.3,
+// eq. Cs2_7 and eq. eta_flux; App. C, eq. A3.1-A3.2)
+//
+// The flux of Xi grad(eta) through side k of a cell is l_k d_k . grad(eta),
+// d_k = Xi_k n_k.  Its tangential part d_{k,tau} = sigma_k t_k / l_k, with
+// sigma_k = (Xi_k N_k) . t_k / (t_k . t_k) for the side vector t_k and
+// N_k = l_k n_k, is written on the scaled outward normals N_a, N_b of the two
+// other sides (co-normal decomposition); by Cramer's rule, with
+// D = t_a x t_b (twice the area),
+//   l_k d_{k,tau} = (-sigma_k (t_k . t_b) / D) N_a + (sigma_k (t_a . t_k) / D) N_b.
+// Each normal derivative N_a . grad(eta) / l_a is the difference quotient
+// (v_a - eta) / d_a, d_a = l_a / T_a, so the cell's estimate of
+// l_k d_{k,tau} . grad(eta) is sum_a coef_a * T_a * (v_a - eta).  The side's
+// term averages the two cells' estimates with opposite signs (each built on
+// its own outward normal), which makes it continuous across the side and
+// exact for linear eta and constant Xi.
+// ---------------------------------------------------------------------------
+
+// Renumbered copies of Xi and of the first solve's eta (cell order in).
+__global__ void k_cross_prep(int n, const int* __restrict__ perm, const double* __restrict__ eps,
+                             const double* __restrict__ logk, const double* __restrict__ chi,
+                             const double* __restrict__ g11, const double* __restrict__ g12,
+                             const double* __restrict__ g22, double nu, double dt,
+                             const double* __restrict__ eta, double* __restrict__ X11,
+                             double* __restrict__ X12, double* __restrict__ X22,
+                             double* __restrict__ eta_r, int32_t* err) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int o = perm[i];
+  const double v = eta[o];
+  if (!isfinite(v)) atomicExch(err, PM_NONFINITE);
+  eta_r[i] = v;
+  double e, K11, K22, x11, x12, x22;
+  if (!cell_xi(o, eps, logk, chi, g11, g12, g22, nu, dt, e, K11, K22, x11, x12, x22, err)) return;
+  X11[i] = x11;
+  X12[i] = x12;
+  X22[i] = x22;
+}
+
+// F[k][i] = l_k times cell i's estimate of d_{k,tau} . grad(eta) for its side
+// k, or 0 where the estimate would need a Neumann side (bit k of avail clear).
+__global__ void __launch_bounds__(256)
+k_cross_est(int n, const int* __restrict__ perm, const int* __restrict__ nb,
+            const int8_t* __restrict__ tag, const uint8_t* __restrict__ avail,
+            const double* __restrict__ T, const double* __restrict__ tx,
+            const double* __restrict__ ty, const double* __restrict__ X11,
+            const double* __restrict__ X12, const double* __restrict__ X22,
+            const double* __restrict__ eta_r, const double* __restrict__ g,
+            double* __restrict__ F) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const unsigned av = avail[i];
+  const double e = eta_r[i];
+  const double x11 = X11[i], x12 = X12[i], x22 = X22[i];
+  double sx[3], sy[3], q[3], y11[3], y12[3], y22[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const size_t s = (size_t)k * n + i;
+    const int o = nb[s];
+    sx[k] = tx[s];
+    sy[k] = ty[s];
+    double v = 0.0;
+    if (o >= 0) {
+      v = eta_r[o];
+      y11[k] = 0.5 * (x11 + X11[o]);
+      y12[k] = 0.5 * (x12 + X12[o]);
+      y22[k] = 0.5 * (x22 + X22[o]);
+    } else {
+      if ((tag[s] & 2) && g) v = g[3 * (size_t)perm[i] + k];
+      y11[k] = x11;
+      y12[k] = x12;
+      y22[k] = x22;
+    }
+    q[k] = T[s] * (v - e);
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int a = k == 2 ? 0 : k + 1, b = k == 0 ? 2 : k - 1;
+    double f = 0.0;
+    if (av & (1u << k)) {
+      const double Nx = sy[k], Ny = -sx[k];
+      const double XNx = y11[k] * Nx + y12[k] * Ny, XNy = y12[k] * Nx + y22[k] * Ny;
+      const double sigma = (XNx * sx[k] + XNy * sy[k]) / (sx[k] * sx[k] + sy[k] * sy[k]);
+      const double D = sx[a] * sy[b] - sy[a] * sx[b];
+      const double ca = -sigma * (sx[k] * sx[b] + sy[k] * sy[b]) / D;
+      const double cb = sigma * (sx[a] * sx[k] + sy[a] * sy[k]) / D;
+      f = ca * q[a] + cb * q[b];
+    }
+    F[(size_t)k * n + i] = f;
+  }
+}
+
+// b_out = b_in + sum_k l_k T_k: the side term is half the difference of the
+// two cells' estimates, the one available estimate alone, or (boundary) the
+// cell's own estimate on CP2 Dirichlet sides and nothing on Neumann sides.
+__global__ void __launch_bounds__(256)
+k_cross_rhs(int n, const int* __restrict__ perm, const int* __restrict__ nb,
+            const int8_t* __restrict__ nbs, const int8_t* __restrict__ tag,
+            const uint8_t* __restrict__ avail, const double* __restrict__ F,
+            const double* b_in, double* b_out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const unsigned av = avail[i];
+  double t[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const size_t s = (size_t)k * n + i;
+    const int o = nb[s];
+    const bool mine = (av >> k) & 1u;
+    const double f = F[s];
+    if (o >= 0) {
+      const int kp = nbs[s];
+      const bool theirs = (avail[o] >> kp) & 1u;
+      const double fo = F[(size_t)kp * n + o];
+      t[k] = mine && theirs ? 0.5 * (f - fo) : (mine ? f : (theirs ? -fo : 0.0));
+    } else {
+      t[k] = mine && (tag[s] & 2) ? f : 0.0;
+    }
+  }
+  const int old = perm[i];
+  b_out[old] = b_in[old] + ((t[0] + t[1]) + t[2]);
+}
+
 }  // namespace pm
 
 // ===========================================================================
@@ -240,11 +386,16 @@ struct pm_mesh {
   int32_t *perm = nullptr, *row_ptr = nullptr, *col = nullptr;
   int32_t *nb = nullptr, *pos = nullptr, *diagpos = nullptr;  // nb/pos: [3][n]
   int8_t* tag = nullptr;                                       // [3][n]
+  int8_t* nbs = nullptr;     // [3][n] side index of the neighbour, -1 on the boundary
+  uint8_t* avail = nullptr;  // [n] bit k: the CP2 cross-term estimate of side k exists
   double *T = nullptr, *tx = nullptr, *ty = nullptr, *area = nullptr;
   // assembly scratch and its input-check flag
   double *X11 = nullptr, *X12 = nullptr, *X22 = nullptr, *M11 = nullptr, *M22 = nullptr;
   int32_t* asm_err = nullptr;
   int32_t* h_err = nullptr;  // pinned
+  // CP2 cross-term workspace (renumbered order)
+  double *eta_r = nullptr, *F = nullptr;  // [n], [3][n]
+  double* b2 = nullptr;                   // [n] second right-hand side, cell order
   // the solver workspace (a set with one system)
   SolveSet set;
   std::vector<void*> allocs;
@@ -381,11 +532,21 @@ int pm_mesh_create(int32_t n_nodes, const double* xy, int32_t n_cells, const int
 
   // per-side arrays in the renumbered order, side-major
   std::vector<int32_t> nb(3 * n), pos(3 * n), diagpos(n);
-  std::vector<int8_t> tag(3 * n);
+  std::vector<int8_t> tag(3 * n), nbs(3 * n);
+  std::vector<uint8_t> avail(n);
   std::vector<double> T(3 * n), tx(3 * n), ty(3 * n), area(n);
   for (size_t i = 0; i < n; ++i) {
     const size_t old = hs.perm[i];
     area[i] = hs.area[old];
+    // a cross-term estimate for side j uses the two other sides, each either
+    // interior or a CP2 Dirichlet side
+    uint8_t usable = 0;
+    for (int j = 0; j < 3; ++j)
+      if (hs.nbr[3 * old + j] >= 0 || (hs.tag[3 * old + j] & 2)) usable |= (uint8_t)(1u << j);
+    for (int j = 0; j < 3; ++j) {
+      const unsigned others = (1u << ((j + 1) % 3)) | (1u << ((j + 2) % 3));
+      if ((usable & others) == others) avail[i] |= (uint8_t)(1u << j);
+    }
     for (int32_t k = hs.row_ptr[i]; k < hs.row_ptr[i + 1]; ++k)
       if (hs.col[k] == (int32_t)i) diagpos[i] = k;
     for (int j = 0; j < 3; ++j) {
@@ -397,6 +558,7 @@ int pm_mesh_create(int32_t n_nodes, const double* xy, int32_t n_cells, const int
         for (int32_t k = hs.row_ptr[i]; k < hs.row_ptr[i + 1]; ++k)
           if (hs.col[k] == nb[s]) pos[s] = k;
       tag[s] = hs.tag[so];
+      nbs[s] = (int8_t)hs.nbr_side[so];
       T[s] = hs.T[so];
       tx[s] = hs.tx[so];
       ty[s] = hs.ty[so];
@@ -415,6 +577,11 @@ int pm_mesh_create(int32_t n_nodes, const double* xy, int32_t n_cells, const int
   ALLOC(m->pos, 3 * n);
   ALLOC(m->diagpos, n);
   ALLOC(m->tag, 3 * n);
+  ALLOC(m->nbs, 3 * n);
+  ALLOC(m->avail, n);
+  ALLOC(m->eta_r, n);
+  ALLOC(m->F, 3 * n);
+  ALLOC(m->b2, n);
   ALLOC(m->T, 3 * n);
   ALLOC(m->tx, 3 * n);
   ALLOC(m->ty, 3 * n);
@@ -443,6 +610,7 @@ int pm_mesh_create(int32_t n_nodes, const double* xy, int32_t n_cells, const int
       {m->col, hs.col.data(), 4 * (size_t)m->nnz}, {m->nb, nb.data(), 12 * n},
       {m->pos, pos.data(), 12 * n},            {m->diagpos, diagpos.data(), 4 * n},
       {m->tag, tag.data(), 3 * n},             {m->T, T.data(), 24 * n},
+      {m->nbs, nbs.data(), 3 * n},             {m->avail, avail.data(), n},
       {m->tx, tx.data(), 24 * n},              {m->ty, ty.data(), 24 * n},
       {m->area, area.data(), 8 * n},
   };
@@ -548,6 +716,134 @@ int pcg_adjoint(pm_mesh* m, int32_t kind, const pm_cell_params* prm, double nu, 
   PM_HIP(hipGetLastError());
   PM_HIP(hipStreamSynchronize(s));
   return st;
+}
+
+}  // extern "C"
+
+namespace {
+
+// The three kernels of cp2_cross_rhs, each bracketed by an event pair when ev
+// is given (ev[0..5]).
+void launch_cross(pm_mesh* m, const pm_cell_params* prm, double nu, double dt, const double* g,
+                  const double* eta, const double* b_in, double* b_out, hipStream_t s,
+                  hipEvent_t* ev) {
+  const int nbk = blocks_for(m->n, 256);
+  if (ev) (void)hipEventRecord(ev[0], s);
+  k_cross_prep<<<nbk, 256, 0, s>>>(m->n, m->perm, prm->eps, prm->logk, prm->chi, prm->g11,
+                                   prm->g12, prm->g22, nu, dt, eta, m->X11, m->X12, m->X22,
+                                   m->eta_r, m->asm_err);
+  if (ev) (void)hipEventRecord(ev[1], s);
+  if (ev) (void)hipEventRecord(ev[2], s);
+  k_cross_est<<<nbk, 256, 0, s>>>(m->n, m->perm, m->nb, m->tag, m->avail, m->T, m->tx, m->ty,
+                                  m->X11, m->X12, m->X22, m->eta_r, g, m->F);
+  if (ev) (void)hipEventRecord(ev[3], s);
+  if (ev) (void)hipEventRecord(ev[4], s);
+  k_cross_rhs<<<nbk, 256, 0, s>>>(m->n, m->perm, m->nb, m->nbs, m->tag, m->avail, m->F, b_in,
+                                  b_out);
+  if (ev) (void)hipEventRecord(ev[5], s);
+}
+
+int cross_args_ok(const pm_mesh* m, const pm_cell_params* prm, double nu, double dt,
+                  const double* eta, const double* b_in, const double* b_out, const char* who) {
+  if (!m || !prm || !prm->eps || !prm->logk || !eta || !b_in || !b_out || !(dt > 0.0) ||
+      !(nu >= 0.0) || !std::isfinite(nu) || !std::isfinite(dt)) {
+    set_error(PM_INVALID_ARG, std::string(who) + ": invalid argument");
+    return PM_INVALID_ARG;
+  }
+  return PM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cp2_cross_rhs(pm_mesh* m, const pm_cell_params* prm, double nu, double dt, const double* g,
+                  const double* eta_tilde, const double* b_in, double* b_out, hipStream_t s) {
+  if (int r = cross_args_ok(m, prm, nu, dt, eta_tilde, b_in, b_out, "cp2_cross_rhs")) return r;
+  PM_HIP(hipMemsetAsync(m->asm_err, 0, sizeof(int32_t), s));
+  launch_cross(m, prm, nu, dt, g, eta_tilde, b_in, b_out, s, nullptr);
+  PM_HIP(hipGetLastError());
+  PM_HIP(hipMemcpyAsync(m->h_err, m->asm_err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  PM_HIP(hipStreamSynchronize(s));
+  if (*m->h_err) {
+    set_error(*m->h_err, "cp2_cross_rhs: invalid or non-finite cell parameters or eta");
+    return *m->h_err;
+  }
+  return PM_OK;
+}
+
+int cp2_solve_two_step(pm_mesh* m, const double* val64, const pm_cell_params* prm, double nu,
+                       double dt, const double* g, const double* b, double* eta_tilde, double* eta,
+                       const pm_opts* opts, pm_info* info, hipStream_t s) {
+  if (!m || !val64 || !b || !eta_tilde || !eta || eta == eta_tilde || eta == b ||
+      eta_tilde == b) {
+    set_error(PM_INVALID_ARG, "cp2_solve_two_step: null or aliased vectors");
+    return PM_INVALID_ARG;
+  }
+  if (int r = cross_args_ok(m, prm, nu, dt, eta_tilde, b, eta, "cp2_solve_two_step")) return r;
+  pm_opts o;
+  pm_opts_default(&o);
+  if (opts) o = *opts;
+  o.x0_is_zero = 1;
+  const int st1 = pcg_solve(m, val64, b, eta_tilde, &o, info, s);
+  if (st1 < 0) return st1;
+  if (int r = cp2_cross_rhs(m, prm, nu, dt, g, eta_tilde, b, m->b2, s)) return r;
+  PM_HIP(hipMemcpyAsync(eta, eta_tilde, sizeof(double) * (size_t)m->n, hipMemcpyDeviceToDevice, s));
+  o.x0_is_zero = 0;
+  const int st2 = pcg_solve(m, val64, m->b2, eta, &o, info ? info + 1 : nullptr, s);
+  if (st2 < 0) return st2;
+  return st1 != PM_OK ? st1 : st2;
+}
+
+int pm_time_cross(pm_mesh* m, const pm_cell_params* prm, double nu, double dt, const double* g,
+                  const double* eta_tilde, const double* b_in, double* b_out, int32_t n_launch,
+                  hipStream_t s, double* ms, double* bytes) {
+  if (int r = cross_args_ok(m, prm, nu, dt, eta_tilde, b_in, b_out, "pm_time_cross")) return r;
+  if (n_launch < 1 || !ms || b_in == b_out) {
+    set_error(PM_INVALID_ARG, "pm_time_cross: n_launch < 1, ms null or b_in == b_out");
+    return PM_INVALID_ARG;
+  }
+  hipEvent_t ev[6];
+  for (auto& e : ev) PM_HIP(hipEventCreate(&e));
+  double acc[3] = {0.0, 0.0, 0.0};
+  PM_HIP(hipMemsetAsync(m->asm_err, 0, sizeof(int32_t), s));
+  launch_cross(m, prm, nu, dt, g, eta_tilde, b_in, b_out, s, nullptr);  // warm-up
+  int st = PM_OK;
+  for (int it = 0; it < n_launch && st == PM_OK; ++it) {
+    launch_cross(m, prm, nu, dt, g, eta_tilde, b_in, b_out, s, ev);
+    if (hipEventSynchronize(ev[5]) != hipSuccess) st = PM_HIP_ERROR;
+    for (int k = 0; k < 3 && st == PM_OK; ++k) {
+      float t = 0.0f;
+      if (hipEventElapsedTime(&t, ev[2 * k], ev[2 * k + 1]) != hipSuccess) st = PM_HIP_ERROR;
+      acc[k] += t;
+    }
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  if (st != PM_OK) {
+    set_error(st, "pm_time_cross: event timing failed");
+    return st;
+  }
+  PM_HIP(hipMemcpyAsync(m->h_err, m->asm_err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  PM_HIP(hipStreamSynchronize(s));
+  if (*m->h_err) {
+    set_error(*m->h_err, "pm_time_cross: invalid or non-finite cell parameters or eta");
+    return *m->h_err;
+  }
+  for (int k = 0; k < 3; ++k) ms[k] = acc[k] / n_launch;
+  if (bytes) {
+    // Algorithmic bytes (every array element read or written once):
+    //   prep  perm, eta, eps, logk (+ chi, g11, g12, g22 when given) in; Xi (3) and eta out
+    //   est   avail, eta, Xi (3), per side nb, tag, T, tx, ty in; F (3 per cell) out
+    //   rhs   perm, avail, F (3), per side nb, nbs, tag, b_in in; b_out out
+    // (Dirichlet values g are read on boundary sides only and not counted.)
+    const double n = m->n;
+    const int given = (prm->chi != nullptr) + (prm->g11 != nullptr) + (prm->g12 != nullptr) +
+                      (prm->g22 != nullptr);
+    bytes[0] = n * (4 + 8 + 16 + 8.0 * given + 24 + 8);
+    bytes[1] = n * (1 + 8 + 24 + 3 * (4 + 1 + 8 + 8 + 8) + 24);
+    bytes[2] = n * (4 + 1 + 24 + 3 * (4 + 1 + 1) + 8 + 8);
+  }
+  return PM_OK;
 }
 
 int pm_time_kernel(pm_mesh* m, int32_t which, int32_t n_launch, hipStream_t s, double* ms,

@@ -8,7 +8,8 @@ benchmark uses (tuned tile, block and schedule; default options).
     1e-9.
   * anisotropic channel, 3,998,952 triangles (CP2): structure bit-exact and
     the residual property for float64 and mixed (an oracle solve at this size
-    takes many minutes).
+    takes many minutes); the CP2 cross terms on every cell against the oracle
+    and the residual property of the two-solve sequence.
   * the 64-system log-normal batch (50k-500k triangles each) on the GPU; the
     residual property on eight systems under the oracle's matrices.
   * adjoint on the 1M channel (loss: squared misfit at 256 probe cells): the
@@ -132,6 +133,32 @@ def test_aniso_channel_4M_structure_and_residual():
     diff = np.linalg.norm(xs[1] - xs[0]) / np.linalg.norm(xs[0])
     log(f"aniso 4M: mixed vs float64 solution {diff:.2e}")
     assert diff <= 1e-8
+
+
+def test_aniso_channel_4M_cross_terms_and_two_step():
+    """CP2 cross terms on every cell of the 4M anisotropic channel against the
+    oracle (tolerance of tests/test_gpu_crossflux.py), and the residual
+    property of both solves of the two-solve sequence."""
+    from oracle import crossflux as ocf
+
+    c = dict(channel_case(552, 3, True), key=(552, 3, True))
+    w = c["w"]
+    A = oracle_system(552, 3, True, "cp2")["A"]
+    val = B().assemble_corrector(c["mesh"], oasm.CP2, c["prm"], w["nu"], w["dt"])["val64"]
+    b = w["rhs"]["cp2"]
+    bt = torch.tensor(b, device=c["dev"])
+    eta, eta_t, infos = B().cp2_solve_two_step(c["mesh"], val, c["prm"], w["nu"], w["dt"], bt)
+    eta_t_h = eta_t.cpu().numpy()
+    b2 = B().cp2_cross_rhs(c["mesh"], c["prm"], w["nu"], w["dt"], eta_t, bt).cpu().numpy()
+    ref = ocf.cross_terms(c["geo"], w["params"], w["nu"], w["dt"], eta_t_h)
+    tol = 32 * 2.0 ** -53 * (ref["scale"] + np.abs(b) + np.abs(ref["cross"]))
+    assert np.all(np.abs(b2 - (b + ref["cross"])) <= tol)
+    perm = c["perm"]
+    r1 = opcg.rel_residual(A, b[perm], eta_t_h[perm])
+    r2 = opcg.rel_residual(A, b2[perm], eta.cpu().numpy()[perm])
+    log(f"aniso 4M two-step: iterations {infos[0]['iters']} + {infos[1]['iters']}, residuals "
+        f"{r1:.2e} {r2:.2e}, |cross|/|b| {np.linalg.norm(ref['cross']) / np.linalg.norm(b):.3f}")
+    assert [i["status"] for i in infos] == [0, 0] and r1 <= 1e-10 and r2 <= 1e-10
 
 
 @functools.lru_cache(maxsize=None)
