@@ -21,6 +21,9 @@ Modules
   crossflux  co-normal tangential flux terms of the CP2 and the right-hand
              side B_2 of its second solve (Sec. 3.2.3, eq. Cs2_7,
              eq. eta_flux; App. C, eq. A3.1-A3.2)
+  cp1coupled the x/y coupling of the CP1 through the anisotropic mass
+             tensor and the paper's loop over the two scalar solves
+             (Sec. 3.2.2, eq. cs1_sys2, eq. CS1_sys_coeff; App. B, eq. A1)
 
 Parity status: every function above is pinned by tests/test_oracle_*.py
 against closed forms, invariants, special cases or brute force; none is

@@ -6,7 +6,7 @@ Each builder returns a dict with
             bit 1 = Dirichlet side of CP2 (Neumann otherwise)
   params    eps, logk, chi, g11, g12, g22 per cell (float64)
   nu, dt    kinematic viscosity and time step
-  rhs       right-hand sides per corrector kind ("cp1x", "cp2")
+  rhs       right-hand sides per corrector kind ("cp1x", "cp1y", "cp2")
   name, recipe
 
 Recipes
@@ -62,6 +62,7 @@ def square_inclusion(npts=64, jitter=0.3, seed=1):
         "rhs": {
             "cp2": fields.boundary_flux_rhs(mesh, meshes.G_LEFT, -1.0),
             "cp1x": 1e-6 * fields.smooth_field(c, seed + 10),
+            "cp1y": 1e-6 * fields.smooth_field(c, seed + 11),
             "random": fields.random_rhs(n, seed + 20),
         },
         "recipe": f"unit square {npts}x{npts} grid jitter {jitter}h seed {seed}",
@@ -85,6 +86,7 @@ def channel(n_rows=276, seed=2, aniso=False):
         "rhs": {
             "cp2": fields.boundary_flux_rhs(mesh, meshes.G_LEFT, -1.0),
             "cp1x": 1e-6 * fields.smooth_field(c, seed + 10),
+            "cp1y": 1e-6 * fields.smooth_field(c, seed + 11),
             "random": fields.random_rhs(n, seed + 20),
         },
         "recipe": f"4x1 channel, {n_rows} coarse rows, refined 4x at the block, seed {seed}",
