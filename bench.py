@@ -14,7 +14,8 @@ Workloads (--workload)
   channel_aniso  the same recipe at ~4.0M triangles with anisotropic K (ratio
                  100 rotated 30 deg); CP2 per step; also reports the two-solve
                  CP2 sequence (cross terms of the first solution on the second
-                 right-hand side) and its cross-term kernels
+                 right-hand side) and its cross-term kernels, and the coupled
+                 CP1 solved by the paper's loop over the x and y systems
   square         unit square 64x64 jittered grid (~8k triangles); CP2
   batch          64 unit squares of 50k-500k triangles with log-normal K;
                  one batched CP2 solve per step
@@ -269,6 +270,27 @@ def main():
         log(f"  two-step: {two_step['iters']} iterations, {wall2 * 1e3:.1f} ms; cross kernels "
             + ", ".join(f"{k} {v['ms'] * 1e3:.1f}us {v['GBs']:.0f}GB/s" for k, v in ck.items()))
 
+    cp1c = None
+    if wl == "channel_aniso":
+        # coupled CP1 by the paper's loop (App. B) at its toll 1e-3, at most
+        # ten coupled passes (it converges slowly on this anisotropic block)
+        log("timing the coupled CP1")
+        vx = B.assemble_corrector(mesh0, B.PM_CP1X, prm0, w0["nu"], w0["dt"])["val64"]
+        vy = B.assemble_corrector(mesh0, B.PM_CP1Y, prm0, w0["nu"], w0["dt"])["val64"]
+        bx = torch.tensor(w0["rhs"]["cp1x"], device=dev)
+        by = torch.tensor(w0["rhs"]["cp1y"], device=dev)
+        B.cp1_solve_coupled(mesh0, prm0, w0["nu"], w0["dt"], vx, vy, bx, by, max_outer=0)  # tune
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        u, v, ic = B.cp1_solve_coupled(mesh0, prm0, w0["nu"], w0["dt"], vx, vy, bx, by, toll=1e-3,
+                                       max_outer=10)
+        torch.cuda.synchronize()
+        wallc = time.perf_counter() - t
+        cp1c = {"ms": wallc * 1e3, "toll": 1e-3, "max_passes": 10, "passes": ic["outer"],
+                "err": ic["err"],
+                "iters": [ic["x"]["iters"], ic["y"]["iters"]], "status": ic["status"]}
+        log(f"  coupled CP1: {ic['outer']} passes, iterations {cp1c['iters']}, {wallc * 1e3:.1f} ms")
+
     sequential = None
     if batch is not None:
         # the same systems solved one after another with pcg_solve
@@ -367,6 +389,7 @@ def main():
         "mixed": mixed,
         "sequential": sequential,
         "cp2_two_step": two_step,
+        "cp1_coupled": cp1c,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

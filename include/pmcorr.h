@@ -13,7 +13,7 @@
  * GPU (single systems or batches of systems of uneven size), with a
  * hand-written adjoint for gradients with respect to the cell parameters and
  * the co-normal cross terms that form the right-hand side of the second CP2
- * solve.
+ * solve, and the coupled anisotropic CP1.
  *
  * Conventions shared by every entry point
  *   - Triangles are given counter-clockwise; side j of triangle e is the side
@@ -331,6 +331,45 @@ int cp2_cross_rhs(pm_mesh* mesh, const pm_cell_params* params, double nu, double
 int cp2_solve_two_step(pm_mesh* mesh, const double* val64, const pm_cell_params* params, double nu,
                        double dt, const double* g_dirichlet, const double* b, double* eta_tilde,
                        double* eta, const pm_opts* opts, pm_info* info, hipStream_t stream);
+
+/*
+ * Coupled CP1 velocity correction for anisotropic permeability (Sec. 3.2.2,
+ * eq. cs1_sys2 and eq. CS1_sys_coeff; App. B, eq. A1).  The mass tensor's
+ * off-diagonal M12 = nu eps Kfrak_12 couples the two components through the
+ * cell term m_e = M12_e A_e:
+ *   A_x u + m v = b_x,   m u + A_y v = b_y.
+ * Following App. B, both scalar systems are solved without the coupling
+ * (zero initial guess), then up to max_outer passes re-solve both with the
+ * coupling taken from the other component's previous iterate (both from
+ * the same iterate), each solve warm-started at that component's previous
+ * iterate, until
+ *   err = min(err_x, err_y) <= toll,  err_x = sqrt(||u' - u||_2) / sqrt(||u||_2)
+ * (likewise y; the square roots are as printed, so err <= toll bounds a
+ * relative change by toll^2; a zero iterate counts as settled only if it
+ * stays zero).  The two systems of a pass are solved together as a batch of
+ * two with pcg_solve_batched's algorithm and opts (x0_is_zero is ignored).
+ *   params, nu, dt  as given to assemble_corrector
+ *   val_x, val_y    device [nnz]: the PM_CP1X and PM_CP1Y matrices
+ *   b_x, b_y        device [n_cells], cell order (Dirichlet lifts included)
+ *   u, v            device [n_cells] out, cell order; distinct
+ *   toll            >= 0 (the paper uses 1e-4 to 1e-3)
+ *   info            host [2] out, nullable: per component, iters summed
+ *                   over all passes, the first non-OK status, and the last
+ *                   solve's residual
+ *   n_outer         host out, nullable: coupled passes run
+ *   err             host out, nullable: err of the last pass (+inf if none)
+ * Returns PM_OK when the test was met (or max_outer is 0), PM_MAXIT when
+ * max_outer passes did not meet it, else the first non-OK solve status.  The
+ * first call on a mesh creates a two-system batch of it (with its own solver
+ * workspace) and 2 nnz + 7 n doubles more, kept until pm_mesh_destroy.  The loop is block Jacobi
+ * on the coupled system, which is symmetric positive definite, so it
+ * converges to the coupled solution.
+ */
+int cp1_solve_coupled(pm_mesh* mesh, const pm_cell_params* params, double nu, double dt,
+                      const double* val_x, const double* val_y, const double* b_x,
+                      const double* b_y, double* u, double* v, double toll, int32_t max_outer,
+                      const pm_opts* opts, pm_info* info, int32_t* n_outer, double* err,
+                      hipStream_t stream);
 
 /*
  * Measurement hook for cp2_cross_rhs: runs it n_launch times (after one

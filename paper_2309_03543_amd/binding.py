@@ -93,6 +93,8 @@ def lib():
             "cp2_cross_rhs": (C.c_int, [P, P, D, D, P, P, P, P, P]),
             "pm_time_cross": (C.c_int, [P, P, D, D, P, P, P, P, I32, P, P, P]),
             "cp2_solve_two_step": (C.c_int, [P, P, P, D, D, P, P, P, P, P, P, P]),
+            "cp1_solve_coupled": (C.c_int, [P, P, D, D, P, P, P, P, P, P, D, I32, P, P, P, P,
+                                            P]),
         }
         for name, (res, args) in sig.items():
             if hasattr(L, name):
@@ -347,6 +349,28 @@ def cp2_solve_two_step(mesh: Mesh, val64, params, nu, dt, b, g_dirichlet=None, s
     return eta, eta_t, [i.as_dict() for i in infos]
 
 
+def cp1_solve_coupled(mesh: Mesh, params, nu, dt, val_x, val_y, b_x, b_y, toll=1e-4,
+                      max_outer=50, stream=None, **opts):
+    """Coupled CP1 by the loop of the paper's App. B.  Returns (u, v, info)
+    with info = {"status", "outer", "err", "x": info of the x solves,
+    "y": ...}; negative statuses raise."""
+    import torch
+
+    u = torch.empty_like(b_x)
+    v = torch.empty_like(b_y)
+    o = make_opts(**opts)
+    infos = (pm_info * 2)()
+    nout = C.c_int32()
+    err = C.c_double()
+    p, _keep = _params(params)
+    st = _check(lib().cp1_solve_coupled(mesh.handle, C.addressof(p), nu, dt, _ptr(val_x),
+                                        _ptr(val_y), _ptr(b_x), _ptr(b_y), _ptr(u), _ptr(v),
+                                        float(toll), int(max_outer), C.addressof(o), infos,
+                                        C.byref(nout), C.byref(err), _stream(stream)))
+    return u, v, {"status": st, "outer": nout.value, "err": err.value,
+                  "x": infos[0].as_dict(), "y": infos[1].as_dict()}
+
+
 def pm_time_cross(mesh: Mesh, params, nu, dt, eta_tilde, b_in, n_launch: int, g_dirichlet=None,
                   stream=None):
     """Mean ms and bytes per launch of the three cross-term kernels."""
@@ -383,5 +407,5 @@ EXPORTED = [
     "pm_mesh_destroy", "pm_mesh_get_stats", "pm_mesh_export", "assemble_corrector", "pcg_solve",
     "pm_batch_create", "pm_batch_destroy", "pm_batch_offsets", "pcg_solve_batched", "pcg_adjoint",
     "pm_time_kernel", "pm_last_launch", "cp2_cross_rhs", "pm_time_cross",
-    "cp2_solve_two_step",
+    "cp2_solve_two_step", "cp1_solve_coupled",
 ]

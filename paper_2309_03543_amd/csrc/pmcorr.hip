@@ -54,8 +54,7 @@ int get_error(char* buf, int32_t len) {
 // Assembly kernels (eq. CS1_sys_coeff, eq. Cs2_4, eq. CS2_sys_coeff)
 // ---------------------------------------------------------------------------
 
-// The caller's data of cell o: Kfrak = chi exp(-s) G (its diagonal in K11,
-// K22) and Xi = eps dt S^{-1} with S = I + nu eps dt Kfrak, which is eps M^{-1}
+// The caller's data of cell o: Kfrak = chi exp(-s) G (K11, K12, K22) and Xi = eps dt S^{-1} with S = I + nu eps dt Kfrak, which is eps M^{-1}
 // for M = I/dt + nu eps Kfrak.  Flags err and returns false for non-finite or
 // invalid data (eps <= 0, chi < 0, G not positive definite).
 __device__ __forceinline__ bool cell_xi(int o, const double* __restrict__ eps,
@@ -64,8 +63,8 @@ __device__ __forceinline__ bool cell_xi(int o, const double* __restrict__ eps,
                                         const double* __restrict__ g11,
                                         const double* __restrict__ g12,
                                         const double* __restrict__ g22, double nu, double dt,
-                                        double& e, double& K11, double& K22, double& X11,
-                                        double& X12, double& X22, int32_t* err) {
+                                        double& e, double& K11, double& K12, double& K22,
+                                        double& X11, double& X12, double& X22, int32_t* err) {
   e = eps[o];
   const double s = logk[o];
   const double ch = chi ? chi[o] : 1.0;
@@ -83,7 +82,7 @@ __device__ __forceinline__ bool cell_xi(int o, const double* __restrict__ eps,
   const double k = ch * exp(-s);
   K11 = k * a11;
   K22 = k * a22;
-  const double K12 = k * a12;
+  K12 = k * a12;
   const double c = nu * e * dt;
   const double S11 = 1.0 + c * K11, S12 = c * K12, S22 = 1.0 + c * K22;
   const double det = S11 * S22 - S12 * S12;
@@ -104,8 +103,9 @@ __global__ void k_cell_tensors(int n, const int* __restrict__ perm, const double
                                double* __restrict__ M22, int32_t* err) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  double e, K11, K22, x11, x12, x22;
-  if (!cell_xi(perm[i], eps, logk, chi, g11, g12, g22, nu, dt, e, K11, K22, x11, x12, x22, err))
+  double e, K11, K12, K22, x11, x12, x22;
+  if (!cell_xi(perm[i], eps, logk, chi, g11, g12, g22, nu, dt, e, K11, K12, K22, x11, x12, x22,
+               err))
     return;
   M11[i] = 1.0 / dt + nu * e * K11;
   M22[i] = 1.0 / dt + nu * e * K22;
@@ -270,8 +270,9 @@ __global__ void k_cross_prep(int n, const int* __restrict__ perm, const double* 
   const double v = eta[o];
   if (!isfinite(v)) atomicExch(err, PM_NONFINITE);
   eta_r[i] = v;
-  double e, K11, K22, x11, x12, x22;
-  if (!cell_xi(o, eps, logk, chi, g11, g12, g22, nu, dt, e, K11, K22, x11, x12, x22, err)) return;
+  double e, K11, K12, K22, x11, x12, x22;
+  if (!cell_xi(o, eps, logk, chi, g11, g12, g22, nu, dt, e, K11, K12, K22, x11, x12, x22, err))
+    return;
   X11[i] = x11;
   X12[i] = x12;
   X22[i] = x22;
@@ -361,6 +362,62 @@ k_cross_rhs(int n, const int* __restrict__ perm, const int* __restrict__ nb,
   b_out[old] = b_in[old] + ((t[0] + t[1]) + t[2]);
 }
 
+// ---------------------------------------------------------------------------
+// Coupled CP1 (Sec. 3.2.2, eq. cs1_sys2 and eq. CS1_sys_coeff; App. B,
+// eq. A1): with anisotropic permeability M12 = nu eps Kfrak_12 couples the x
+// and y systems through the cell term M12 A_e.  The loop of App. B solves
+// both scalar systems, then repeatedly re-solves them with the coupling
+// evaluated at the other component's previous iterate.  Vectors of the pair
+// are packed [x | y] in cell order.
+// ---------------------------------------------------------------------------
+
+// m_e = M12_e A_e in cell order (one thread per renumbered cell).
+__global__ void k_cp1_mass(int n, const int* __restrict__ perm, const double* __restrict__ eps,
+                           const double* __restrict__ logk, const double* __restrict__ chi,
+                           const double* __restrict__ g11, const double* __restrict__ g12,
+                           const double* __restrict__ g22, double nu, double dt,
+                           const double* __restrict__ area, double* __restrict__ mA,
+                           int32_t* err) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int o = perm[i];
+  double e, K11, K12, K22, x11, x12, x22;
+  if (!cell_xi(o, eps, logk, chi, g11, g12, g22, nu, dt, e, K11, K12, K22, x11, x12, x22, err))
+    return;
+  mA[o] = (nu * e * K12) * area[i];
+}
+
+// Right-hand sides of a coupled pass from the previous iterate xp = [u | v]:
+// [b_x - m v | b_y - m u]; the iterate is kept in prev for the change test.
+__global__ void k_cp1_couple(int n, const double* __restrict__ mA, const double* __restrict__ bx,
+                             const double* __restrict__ by, const double* __restrict__ xp,
+                             double* __restrict__ bp, double* __restrict__ prev) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const double u = xp[e], v = xp[(size_t)n + e], m = mA[e];
+  bp[e] = bx[e] - m * v;
+  bp[(size_t)n + e] = by[e] - m * u;
+  prev[e] = u;
+  prev[(size_t)n + e] = v;
+}
+
+// Per-block partial sums of |u' - u|^2, |u|^2, |v' - v|^2, |v|^2 (new
+// iterate xp, previous prev), grid-stride, written to part[block][4].
+__global__ void __launch_bounds__(256)
+k_cp1_change(int n, const double* __restrict__ xp, const double* __restrict__ prev,
+             double* __restrict__ part) {
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+    const double u0 = prev[e], v0 = prev[(size_t)n + e];
+    const double du = xp[e] - u0, dv = xp[(size_t)n + e] - v0;
+    acc[0] += du * du;
+    acc[1] += u0 * u0;
+    acc[2] += dv * dv;
+    acc[3] += v0 * v0;
+  }
+  block_partial<4>(acc, part + 4 * (size_t)blockIdx.x);
+}
+
 }  // namespace pm
 
 // ===========================================================================
@@ -396,6 +453,11 @@ struct pm_mesh {
   // CP2 cross-term workspace (renumbered order)
   double *eta_r = nullptr, *F = nullptr;  // [n], [3][n]
   double* b2 = nullptr;                   // [n] second right-hand side, cell order
+  // coupled CP1: a two-system batch of this mesh (x, y) and its packed
+  // vectors, created by the first cp1_solve_coupled call
+  pm_batch* pair = nullptr;
+  double *pv = nullptr, *pb = nullptr, *px = nullptr, *pprev = nullptr;  // [2 nnz], [2n] x3
+  double *mA = nullptr, *ppart = nullptr, *h_part = nullptr;           // [n], [blocks][4], pinned
   // the solver workspace (a set with one system)
   SolveSet set;
   std::vector<void*> allocs;
@@ -422,6 +484,8 @@ int dalloc(pm_mesh* m, T** ptr, size_t count) {
 
 void free_mesh(pm_mesh* m) {
   if (!m) return;
+  if (m->pair) pm_batch_destroy(m->pair);
+  if (m->h_part) (void)hipHostFree(m->h_part);
   set_free(m->set);
   for (void* p : m->allocs) (void)hipFree(p);
   if (m->h_err) (void)hipHostFree(m->h_err);
@@ -793,6 +857,134 @@ int cp2_solve_two_step(pm_mesh* m, const double* val64, const pm_cell_params* pr
   const int st2 = pcg_solve(m, val64, m->b2, eta, &o, info ? info + 1 : nullptr, s);
   if (st2 < 0) return st2;
   return st1 != PM_OK ? st1 : st2;
+}
+
+}  // extern "C"
+
+namespace {
+
+constexpr int kChangeBlocks = 512;
+
+// The pair batch and its workspace, on first use.
+int ensure_pair(pm_mesh* m) {
+  if (m->pair) return PM_OK;
+  pm_mesh* two[2] = {m, m};
+  pm_batch* b = nullptr;
+  if (int r = pm_batch_create(2, two, &b)) return r;
+  const size_t n = m->n;
+  int r = PM_OK;
+  if ((r = dalloc(m, &m->pv, 2 * (size_t)m->nnz)) || (r = dalloc(m, &m->pb, 2 * n)) ||
+      (r = dalloc(m, &m->px, 2 * n)) || (r = dalloc(m, &m->pprev, 2 * n)) ||
+      (r = dalloc(m, &m->mA, n)) || (r = dalloc(m, &m->ppart, 4 * (size_t)kChangeBlocks))) {
+    pm_batch_destroy(b);
+    return r;
+  }
+  hipError_t e = hipHostMalloc((void**)&m->h_part, sizeof(double) * 4 * kChangeBlocks,
+                               hipHostMallocDefault);
+  if (e != hipSuccess) {
+    pm_batch_destroy(b);
+    set_error(PM_HIP_ERROR, std::string("hipHostMalloc: ") + hipGetErrorString(e));
+    return PM_HIP_ERROR;
+  }
+  m->pair = b;
+  return PM_OK;
+}
+
+// Adds the per-system iteration counts of a batched pair solve to info.
+void add_infos(pm_info* acc, const pm_info* last) {
+  for (int c = 0; c < 2; ++c) {
+    const int32_t it = acc[c].iters + last[c].iters;
+    const int32_t st = acc[c].status != PM_OK ? acc[c].status : last[c].status;
+    acc[c] = last[c];
+    acc[c].iters = it;
+    acc[c].status = st;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int cp1_solve_coupled(pm_mesh* m, const pm_cell_params* prm, double nu, double dt,
+                      const double* val_x, const double* val_y, const double* b_x,
+                      const double* b_y, double* u, double* v, double toll, int32_t max_outer,
+                      const pm_opts* opts, pm_info* info, int32_t* n_outer, double* err,
+                      hipStream_t s) {
+  if (!m || !prm || !prm->eps || !prm->logk || !val_x || !val_y || !b_x || !b_y || !u || !v ||
+      u == v || !(toll >= 0.0) || max_outer < 0 || !(dt > 0.0) || !(nu >= 0.0) ||
+      !std::isfinite(nu) || !std::isfinite(dt)) {
+    set_error(PM_INVALID_ARG, "cp1_solve_coupled: invalid argument");
+    return PM_INVALID_ARG;
+  }
+  pm_opts o;
+  pm_opts_default(&o);
+  if (opts) o = *opts;
+  if (int r = check_opts(o)) return r;
+  if (int r = ensure_pair(m)) return r;
+  const size_t n = m->n, nnz = m->nnz;
+  const int nbk = blocks_for(m->n, 256);
+  PM_HIP(hipMemsetAsync(m->asm_err, 0, sizeof(int32_t), s));
+  k_cp1_mass<<<nbk, 256, 0, s>>>(m->n, m->perm, prm->eps, prm->logk, prm->chi, prm->g11,
+                                 prm->g12, prm->g22, nu, dt, m->area, m->mA, m->asm_err);
+  PM_HIP(hipGetLastError());
+  PM_HIP(hipMemcpyAsync(m->pv, val_x, sizeof(double) * nnz, hipMemcpyDeviceToDevice, s));
+  PM_HIP(hipMemcpyAsync(m->pv + nnz, val_y, sizeof(double) * nnz, hipMemcpyDeviceToDevice, s));
+  PM_HIP(hipMemcpyAsync(m->pb, b_x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  PM_HIP(hipMemcpyAsync(m->pb + n, b_y, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  PM_HIP(hipMemcpyAsync(m->h_err, m->asm_err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  PM_HIP(hipStreamSynchronize(s));
+  if (*m->h_err) {
+    set_error(*m->h_err, "cp1_solve_coupled: invalid or non-finite cell parameters");
+    return *m->h_err;
+  }
+  pm_info acc[2] = {}, last[2] = {};
+  // uncoupled first pass (App. B: the coupling term starts at zero)
+  o.x0_is_zero = 1;
+  int st = pcg_solve_batched(m->pair, m->pv, m->pb, m->px, &o, last, s);
+  add_infos(acc, last);
+  if (st < 0) {
+    if (info) std::memcpy(info, acc, sizeof(acc));
+    return st;
+  }
+  o.x0_is_zero = 0;
+  int pass = 0;
+  double e_min = INFINITY;
+  bool met = false;
+  while (pass < max_outer) {
+    k_cp1_couple<<<nbk, 256, 0, s>>>(m->n, m->mA, b_x, b_y, m->px, m->pb, m->pprev);
+    PM_HIP(hipGetLastError());
+    st = pcg_solve_batched(m->pair, m->pv, m->pb, m->px, &o, last, s);
+    add_infos(acc, last);
+    ++pass;
+    if (st < 0) break;
+    k_cp1_change<<<kChangeBlocks, 256, 0, s>>>(m->n, m->px, m->pprev, m->ppart);
+    PM_HIP(hipGetLastError());
+    PM_HIP(hipMemcpyAsync(m->h_part, m->ppart, sizeof(double) * 4 * kChangeBlocks,
+                          hipMemcpyDeviceToHost, s));
+    PM_HIP(hipStreamSynchronize(s));
+    double sum[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < kChangeBlocks; ++b)
+      for (int k = 0; k < 4; ++k) sum[k] += m->h_part[4 * b + k];
+    // err_c = sqrt(||c' - c||) / sqrt(||c||), a zero iterate settled only if unchanged
+    auto comp = [](double d2, double o2) {
+      if (o2 == 0.0) return d2 == 0.0 ? 0.0 : (double)INFINITY;
+      return std::sqrt(std::sqrt(d2)) / std::sqrt(std::sqrt(o2));
+    };
+    e_min = std::min(comp(sum[0], sum[1]), comp(sum[2], sum[3]));
+    if (e_min <= toll) {
+      met = true;
+      break;
+    }
+  }
+  PM_HIP(hipMemcpyAsync(u, m->px, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  PM_HIP(hipMemcpyAsync(v, m->px + n, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  PM_HIP(hipStreamSynchronize(s));
+  if (info) std::memcpy(info, acc, sizeof(acc));
+  if (n_outer) *n_outer = pass;
+  if (err) *err = pass > 0 ? e_min : INFINITY;
+  if (st < 0) return st;
+  if (st != PM_OK) return st;
+  return met || max_outer == 0 ? PM_OK : PM_MAXIT;
 }
 
 int pm_time_cross(pm_mesh* m, const pm_cell_params* prm, double nu, double dt, const double* g,

@@ -9,7 +9,8 @@ benchmark uses (tuned tile, block and schedule; default options).
   * anisotropic channel, 3,998,952 triangles (CP2): structure bit-exact and
     the residual property for float64 and mixed (an oracle solve at this size
     takes many minutes); the CP2 cross terms on every cell against the oracle
-    and the residual property of the two-solve sequence.
+    and the residual property of the two-solve sequence; the systems of the
+    coupled CP1 loop's second pass under the oracle's matrices.
   * the 64-system log-normal batch (50k-500k triangles each) on the GPU; the
     residual property on eight systems under the oracle's matrices.
   * adjoint on the 1M channel (loss: squared misfit at 256 probe cells): the
@@ -32,7 +33,7 @@ from oracle import pcg as opcg  # noqa: E402
 from synth import workloads  # noqa: E402
 
 pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
-KIND = {"cp1x": oasm.CP1X, "cp2": oasm.CP2}
+KIND = {"cp1x": oasm.CP1X, "cp1y": oasm.CP1Y, "cp2": oasm.CP2}
 
 
 def B():
@@ -159,6 +160,40 @@ def test_aniso_channel_4M_cross_terms_and_two_step():
     log(f"aniso 4M two-step: iterations {infos[0]['iters']} + {infos[1]['iters']}, residuals "
         f"{r1:.2e} {r2:.2e}, |cross|/|b| {np.linalg.norm(ref['cross']) / np.linalg.norm(b):.3f}")
     assert [i["status"] for i in infos] == [0, 0] and r1 <= 1e-10 and r2 <= 1e-10
+
+
+def test_aniso_channel_4M_coupled_cp1():
+    """The coupled CP1 loop (App. B) on the 4M anisotropic channel: after one
+    and after two coupled passes, the oracle's matrices confirm that the
+    second pass solved A_x u2 = b_x - m v1 and A_y v2 = b_y - m u1 to the
+    solver tolerance (the loop restarts from the uncoupled solves on every
+    call and is deterministic, so the first call's result is the second
+    call's first pass)."""
+    from oracle import cp1coupled as occ
+
+    c = dict(channel_case(552, 3, True), key=(552, 3, True))
+    w = c["w"]
+    vx = B().assemble_corrector(c["mesh"], oasm.CP1X, c["prm"], w["nu"], w["dt"])["val64"]
+    vy = B().assemble_corrector(c["mesh"], oasm.CP1Y, c["prm"], w["nu"], w["dt"])["val64"]
+    bx, by = w["rhs"]["cp1x"], w["rhs"]["cp1y"]
+    bxt, byt = torch.tensor(bx, device=c["dev"]), torch.tensor(by, device=c["dev"])
+    runs = []
+    for passes in (1, 2):
+        u, v, info = B().cp1_solve_coupled(c["mesh"], c["prm"], w["nu"], w["dt"], vx, vy, bxt, byt,
+                                           toll=0.0, max_outer=passes)
+        assert info["outer"] == passes and info["status"] == B().PM_MAXIT
+        assert info["x"]["status"] == 0 and info["y"]["status"] == 0
+        runs.append((u.cpu().numpy(), v.cpu().numpy(), info))
+    perm = c["perm"]
+    Ax = oracle_system(552, 3, True, "cp1x")["A"]
+    Ay = oracle_system(552, 3, True, "cp1y")["A"]
+    m = occ.coupling_weights(c["geo"], w["params"], w["nu"], w["dt"])
+    (u1, v1, _), (u2, v2, i2) = runs
+    rx = opcg.rel_residual(Ax, (bx - m * v1)[perm], u2[perm])
+    ry = opcg.rel_residual(Ay, (by - m * u1)[perm], v2[perm])
+    log(f"aniso 4M coupled CP1: err after 1 and 2 passes {runs[0][2]['err']:.3e} "
+        f"{i2['err']:.3e}; pass-2 residuals {rx:.2e} {ry:.2e}")
+    assert rx <= 1e-10 and ry <= 1e-10
 
 
 @functools.lru_cache(maxsize=None)
