@@ -163,3 +163,63 @@ def test_loop_stops_when_either_component_settles():
 
     out = cc.block_iteration(sx, sy, np.zeros(4), np.zeros(4), np.zeros(4), toll=1e-4)
     assert out["outer"] == 1 and out["errs"] == [0.0] and out["converged"]
+
+
+def test_block_inverses_invert_the_cell_blocks():
+    geo, perm, prm, dt, Ax, Ay, m_cell = case(npts=8, random_dir=True)
+    m = m_cell[perm]
+    i11, i12, i22 = cc.block_inverses(Ax, Ay, m)
+    dx, dy = Ax.diagonal(), Ay.diagonal()
+    for e in range(0, geo["n"], 7):
+        Pe = np.array([[dx[e], m[e]], [m[e], dy[e]]])
+        np.testing.assert_allclose(Pe @ np.array([[i11[e], i12[e]], [i12[e], i22[e]]]), np.eye(2),
+                                   atol=1e-13)
+
+
+@pytest.mark.parametrize("random_dir", [False, True])
+def test_coupled_pcg_reaches_the_direct_solution(random_dir):
+    """Block-Jacobi CG on the coupled system against a sparse direct solve of
+    it, for a manufactured pair and a smooth right-hand side."""
+    import scipy.sparse.linalg as spl
+
+    geo, perm, prm, dt, Ax, Ay, m_cell = case(random_dir=random_dir)
+    n = geo["n"]
+    m = m_cell[perm]
+    C = cc.coupled_matrix(Ax, Ay, m)
+    rng = np.random.default_rng(9)
+    xs = np.concatenate([rng.standard_normal(n), rng.standard_normal(n)])
+    b = C @ xs
+    (u, v), info = cc.coupled_pcg(Ax, Ay, m, b[:n], b[n:])
+    assert info["status"] == 0 and info["rel_res_true"] <= 1e-10 and info["iters"] % 50 == 0
+    x = np.concatenate([u, v])
+    assert np.linalg.norm(x - xs) <= 1e-8 * np.linalg.norm(xs)
+    xd = spl.spsolve(C.tocsc(), b)
+    assert np.linalg.norm(x - xd) <= 1e-8 * np.linalg.norm(xd)
+
+
+def test_coupled_pcg_on_the_channel_and_the_loop_limit():
+    """On a small anisotropic channel (eq. aniso block, 11,840 cells) the
+    coupled CG reaches the direct solution, and the loop of App. B converges
+    towards the same solution (slowly: the block's cell tensors are strongly
+    coupled)."""
+    import scipy.sparse.linalg as spl
+
+    w = workloads.channel(30, 3, aniso=True)
+    m_ = w["mesh"]
+    geo = geometry.build(m_["xy"], m_["tri"], w["side_tag"])
+    perm = ordering.rcm(geo["nbr"])
+    Ax = asm.assemble(geo, perm, asm.CP1X, w["params"], w["nu"], w["dt"])["A"]
+    Ay = asm.assemble(geo, perm, asm.CP1Y, w["params"], w["nu"], w["dt"])["A"]
+    m = cc.coupling_weights(geo, w["params"], w["nu"], w["dt"])[perm]
+    n = geo["n"]
+    bx, by = w["rhs"]["cp1x"][perm], w["rhs"]["cp1y"][perm]
+    (u, v), info = cc.coupled_pcg(Ax, Ay, m, bx, by)
+    assert info["status"] == 0
+    xd = spl.spsolve(cc.coupled_matrix(Ax, Ay, m).tocsc(), np.concatenate([bx, by]))
+    assert np.linalg.norm(np.concatenate([u, v]) - xd) <= 1e-9 * np.linalg.norm(xd)
+    fx, fy = spl.factorized(Ax.tocsc()), spl.factorized(Ay.tocsc())
+    lp = cc.block_iteration(lambda r, x0: fx(r), lambda r, x0: fy(r), m, bx, by, toll=1e-3,
+                            max_outer=400)
+    assert lp["converged"] and lp["outer"] > 50
+    e_loop = np.linalg.norm(np.concatenate([lp["u"], lp["v"]]) - xd) / np.linalg.norm(xd)
+    assert e_loop < 1e-3
