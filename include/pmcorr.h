@@ -372,6 +372,37 @@ int cp1_solve_coupled(pm_mesh* mesh, const pm_cell_params* params, double nu, do
                       hipStream_t stream);
 
 /*
+ * The coupled CP1 system of cp1_solve_coupled,
+ *   A_x u + m v = b_x,   m u + A_y v = b_y,   m_e = M12_e A_e,
+ * solved directly by conjugate gradients on both components together, with
+ * the inverse of each cell's 2x2 diagonal block [[A_x,ee, m_e], [m_e, A_y,ee]]
+ * as preconditioner.  This is not the paper's procedure (App. B iterates over
+ * the two scalar systems); the system is symmetric positive definite (nu
+ * times the Laplacian on each component, plus each cell's SPD mass tensor
+ * times A_e, plus the Dirichlet terms), and one solve reaches the limit of
+ * that iteration.  Starting from zero, every opts.replace_every iterations
+ * the true residual ||b - C x||_2 (float64) is evaluated and the solve stops
+ * once it is <= opts.tol ||b||_2; the recursive residual is not replaced.
+ *   params, nu, dt  as given to assemble_corrector (for m)
+ *   val_x, val_y    device [nnz]: the PM_CP1X and PM_CP1Y matrices; their
+ *                   off-diagonals must agree (both are -nu T)
+ *   b_x, b_y        device [n_cells], cell order (Dirichlet lifts included)
+ *   u, v            device [n_cells] out, cell order; distinct
+ *   opts            tol, max_it and replace_every apply; precision must be
+ *                   PM_FP64; the other fields are ignored
+ *   info            host out, nullable: iterations, status, the true
+ *                   relative residual of (u, v) and ||b||
+ * Errors: PM_INVALID_ARG (arguments, off-diagonals that differ, a cell
+ * block that is not positive definite), PM_NONFINITE, PM_BREAKDOWN.  The
+ * first call on a mesh allocates a workspace of 23 n doubles, kept until
+ * pm_mesh_destroy.
+ */
+int cp1_solve_coupled_pcg(pm_mesh* mesh, const pm_cell_params* params, double nu, double dt,
+                          const double* val_x, const double* val_y, const double* b_x,
+                          const double* b_y, double* u, double* v, const pm_opts* opts,
+                          pm_info* info, hipStream_t stream);
+
+/*
  * Measurement hook for cp2_cross_rhs: runs it n_launch times (after one
  * warm-up) with HIP events around each of its three kernels and returns the
  * mean durations in ms (ms[3]: per-cell preparation of Xi and eta~, the

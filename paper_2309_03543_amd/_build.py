@@ -33,6 +33,7 @@ def build(verbose: bool = False) -> str:
         ("pmcorr.hip", COMMON + DEVICE),
         ("solver.hip", COMMON + DEVICE),
         ("batched.hip", COMMON + DEVICE),
+        ("coupled.hip", COMMON + DEVICE),
     ]
     procs = []
     for src, flags in jobs:

@@ -95,6 +95,7 @@ def lib():
             "cp2_solve_two_step": (C.c_int, [P, P, P, D, D, P, P, P, P, P, P, P]),
             "cp1_solve_coupled": (C.c_int, [P, P, D, D, P, P, P, P, P, P, D, I32, P, P, P, P,
                                             P]),
+            "cp1_solve_coupled_pcg": (C.c_int, [P, P, D, D, P, P, P, P, P, P, P, P, P]),
         }
         for name, (res, args) in sig.items():
             if hasattr(L, name):
@@ -371,6 +372,23 @@ def cp1_solve_coupled(mesh: Mesh, params, nu, dt, val_x, val_y, b_x, b_y, toll=1
                   "x": infos[0].as_dict(), "y": infos[1].as_dict()}
 
 
+def cp1_solve_coupled_pcg(mesh: Mesh, params, nu, dt, val_x, val_y, b_x, b_y, stream=None,
+                          **opts):
+    """Coupled CP1 by block-Jacobi CG on both components.  Returns (u, v,
+    info); negative statuses raise."""
+    import torch
+
+    u = torch.empty_like(b_x)
+    v = torch.empty_like(b_y)
+    o = make_opts(**opts)
+    info = pm_info()
+    p, _keep = _params(params)
+    _check(lib().cp1_solve_coupled_pcg(mesh.handle, C.addressof(p), nu, dt, _ptr(val_x),
+                                       _ptr(val_y), _ptr(b_x), _ptr(b_y), _ptr(u), _ptr(v),
+                                       C.addressof(o), C.addressof(info), _stream(stream)))
+    return u, v, info.as_dict()
+
+
 def pm_time_cross(mesh: Mesh, params, nu, dt, eta_tilde, b_in, n_launch: int, g_dirichlet=None,
                   stream=None):
     """Mean ms and bytes per launch of the three cross-term kernels."""
@@ -407,5 +425,5 @@ EXPORTED = [
     "pm_mesh_destroy", "pm_mesh_get_stats", "pm_mesh_export", "assemble_corrector", "pcg_solve",
     "pm_batch_create", "pm_batch_destroy", "pm_batch_offsets", "pcg_solve_batched", "pcg_adjoint",
     "pm_time_kernel", "pm_last_launch", "cp2_cross_rhs", "pm_time_cross",
-    "cp2_solve_two_step", "cp1_solve_coupled",
+    "cp2_solve_two_step", "cp1_solve_coupled", "cp1_solve_coupled_pcg",
 ]

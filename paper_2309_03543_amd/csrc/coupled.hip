@@ -1,0 +1,365 @@
+// Conjugate gradients on the coupled CP1 system (gfx950).
+//
+// With anisotropic permeability the CP1 velocity components are coupled
+// through the off-diagonal of each cell's mass tensor (Sec. 3.2.2,
+// eq. cs1_sys2 and eq. CS1_sys_coeff):
+//   A_x u + m v = b_x,   m u + A_y v = b_y,   m_e = M12_e A_e.
+// The 2n x 2n matrix is nu L (x) I plus the cells' SPD mass blocks plus the
+// Dirichlet terms, so it is SPD and CG applies directly; the preconditioner
+// is the inverse of each cell's 2x2 diagonal block.  Both components of a
+// cell sit together (double2), so each row reads its three weights, shared by
+// the x and y matrices, once for both components.
+//
+// Work is cut into tiles of rows, one block per tile (XCD-aware order).  Two
+// kernels per iteration, no grid-wide waits inside a kernel: each kernel
+// reduces the per-tile partials of the previous one in a fixed order, so
+// every block gets bitwise the same scalar.
+//   k_cc_spmv    r.z of the last update -> beta; p = z + beta p (own rows,
+//                and recomputed with the same expression for the neighbours);
+//                q = C p; partial p.q
+//   k_cc_update  alpha = r.z / p.q; x += alpha p; r -= alpha q; z = P^{-1} r;
+//                partial r.z
+// Every check_every iterations the true residual ||b - C x|| decides the stop
+// (the recursive residual is not replaced).
+//
+// Compiled with -ffp-contract=off.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "coupled.h"
+#include "kernels.h"
+
+namespace pm {
+
+void set_error(int status, const std::string& msg);
+
+namespace {
+
+constexpr int kFlagPattern = 1;    // x and y matrices differ off the diagonal
+constexpr int kFlagNotSpd = 2;     // a cell's 2x2 block is not positive definite
+constexpr int kFlagNonfinite = 3;  // NaN or Inf in the right-hand side
+constexpr int kFlagBreakdown = 4;  // p.q <= 0 or not finite
+
+struct CA {
+  int n, tile_rows, n_tiles;
+  const int* nb;
+  double* w;
+  double* dm;
+  double* inv;
+  double2* b;
+  double2* x;
+  double2* r;
+  double2* z;
+  double2* q;
+  double2* p0;
+  double2* p1;
+  double* part;  // [3][n_tiles]: p.q (or the setup / residual sums), r.z even, r.z odd
+  double* scal;  // r.z of even and odd iterations
+  int32_t* flag;
+};
+
+// Fixed-order block sum of NV values; every thread gets the totals.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV]) {
+  __shared__ double sh[NV][16];
+  __shared__ double res[NV];
+  wave_sum<NV>(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) sh[k][wid] = v[k];
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    double s = 0.0;
+    for (int k = 0; k < nw; ++k) s += sh[threadIdx.x][k];
+    res[threadIdx.x] = s;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = res[k];
+}
+
+// Sum of the t tile partials at part, the same in every block.
+__device__ __forceinline__ double sum_tiles(const double* __restrict__ part, int t) {
+  double v[1] = {0.0};
+  for (int i = threadIdx.x; i < t; i += blockDim.x) v[0] += part[i];
+  block_sum<1>(v);
+  return v[0];
+}
+
+__device__ __forceinline__ void tile_rows(const CA& a, int& tile, int& r0, int& r1) {
+  tile = xcd_block(blockIdx.x, gridDim.x);
+  r0 = tile * a.tile_rows;
+  r1 = min(a.n, r0 + a.tile_rows);
+}
+
+// (C y)_i for the cell pair y (both components of every cell)
+__device__ __forceinline__ double2 apply_row(const CA& a, int i, double2 yi, const double2* y_nb) {
+  const double dx = a.dm[i], dy = a.dm[(size_t)a.n + i], m = a.dm[2 * (size_t)a.n + i];
+  double qx = dx * yi.x + m * yi.y, qy = m * yi.x + dy * yi.y;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const size_t s = (size_t)k * a.n + i;
+    if (a.nb[s] >= 0) {
+      const double wk = a.w[s];
+      qx -= wk * y_nb[k].x;
+      qy -= wk * y_nb[k].y;
+    }
+  }
+  return make_double2(qx, qy);
+}
+
+__global__ void __launch_bounds__(kCoupledBlock)
+k_cc_setup(CA a, const int* __restrict__ perm, const int* __restrict__ pos,
+           const int* __restrict__ diagpos, const double* __restrict__ val_x,
+           const double* __restrict__ val_y, const double* __restrict__ mA,
+           const double* __restrict__ bx, const double* __restrict__ by) {
+  int t, r0, r1;
+  tile_rows(a, t, r0, r1);
+  double acc[2] = {0.0, 0.0};
+  for (int i = r0 + (int)threadIdx.x; i < r1; i += blockDim.x) {
+    const int o = perm[i];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const size_t s = (size_t)k * a.n + i;
+      const int ps = pos[s];
+      double wk = 0.0;
+      if (ps >= 0) {
+        wk = -val_x[ps];
+        if (val_y[ps] != val_x[ps]) atomicExch(a.flag, kFlagPattern);
+      }
+      a.w[s] = wk;
+    }
+    const double dx = val_x[diagpos[i]], dy = val_y[diagpos[i]], m = mA[o];
+    a.dm[i] = dx;
+    a.dm[(size_t)a.n + i] = dy;
+    a.dm[2 * (size_t)a.n + i] = m;
+    const double det = dx * dy - m * m;
+    if (!(dx > 0.0) || !(det > 0.0) || !isfinite(det)) atomicExch(a.flag, kFlagNotSpd);
+    const double i11 = dy / det, i12 = -m / det, i22 = dx / det;
+    a.inv[i] = i11;
+    a.inv[(size_t)a.n + i] = i12;
+    a.inv[2 * (size_t)a.n + i] = i22;
+    const double2 bb = make_double2(bx[o], by[o]);
+    if (!isfinite(bb.x) || !isfinite(bb.y)) atomicExch(a.flag, kFlagNonfinite);
+    const double2 zz = make_double2(i11 * bb.x + i12 * bb.y, i12 * bb.x + i22 * bb.y);
+    a.b[i] = bb;
+    a.x[i] = make_double2(0.0, 0.0);
+    a.r[i] = bb;
+    a.z[i] = zz;
+    acc[0] += bb.x * bb.x + bb.y * bb.y;
+    acc[1] += bb.x * zz.x + bb.y * zz.y;
+  }
+  block_sum<2>(acc);
+  if (threadIdx.x == 0) {
+    a.part[t] = acc[0];                   // ||b||^2
+    a.part[(size_t)a.n_tiles + t] = acc[1];  // r.z of iteration 0
+  }
+}
+
+__global__ void __launch_bounds__(kCoupledBlock) k_cc_spmv(CA a, int k) {
+  if (*a.flag) return;
+  const double rz = sum_tiles(a.part + (size_t)(1 + (k & 1)) * a.n_tiles, a.n_tiles);
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.scal[k & 1] = rz;
+  const double beta = k == 0 ? 0.0 : rz / a.scal[(k - 1) & 1];
+  const double2* __restrict__ pold = (k & 1) ? a.p0 : a.p1;
+  double2* __restrict__ pnew = (k & 1) ? a.p1 : a.p0;
+  int t, r0, r1;
+  tile_rows(a, t, r0, r1);
+  double acc[1] = {0.0};
+  for (int i = r0 + (int)threadIdx.x; i < r1; i += blockDim.x) {
+    double2 pn[3];
+#pragma unroll
+    for (int kk = 0; kk < 3; ++kk) {
+      const int o = a.nb[(size_t)kk * a.n + i];
+      pn[kk] = make_double2(0.0, 0.0);
+      if (o >= 0) {
+        const double2 zo = a.z[o];
+        if (k == 0) {
+          pn[kk] = zo;
+        } else {
+          const double2 po = pold[o];
+          pn[kk] = make_double2(zo.x + beta * po.x, zo.y + beta * po.y);
+        }
+      }
+    }
+    const double2 zi = a.z[i];
+    double2 pi = zi;
+    if (k != 0) {
+      const double2 po = pold[i];
+      pi = make_double2(zi.x + beta * po.x, zi.y + beta * po.y);
+    }
+    pnew[i] = pi;
+    const double2 qi = apply_row(a, i, pi, pn);
+    a.q[i] = qi;
+    acc[0] += pi.x * qi.x + pi.y * qi.y;
+  }
+  block_sum<1>(acc);
+  if (threadIdx.x == 0) a.part[t] = acc[0];
+}
+
+__global__ void __launch_bounds__(kCoupledBlock) k_cc_update(CA a, int k) {
+  if (*a.flag) return;
+  const double pq = sum_tiles(a.part, a.n_tiles);
+  if (!(pq > 0.0) || !isfinite(pq)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicExch(a.flag, kFlagBreakdown);
+    return;
+  }
+  const double alpha = a.scal[k & 1] / pq;
+  const double2* __restrict__ p = (k & 1) ? a.p1 : a.p0;
+  int t, r0, r1;
+  tile_rows(a, t, r0, r1);
+  double acc[1] = {0.0};
+  for (int i = r0 + (int)threadIdx.x; i < r1; i += blockDim.x) {
+    const double2 pi = p[i], qi = a.q[i];
+    double2 xi = a.x[i], ri = a.r[i];
+    xi.x += alpha * pi.x;
+    xi.y += alpha * pi.y;
+    ri.x -= alpha * qi.x;
+    ri.y -= alpha * qi.y;
+    const double i11 = a.inv[i], i12 = a.inv[(size_t)a.n + i], i22 = a.inv[2 * (size_t)a.n + i];
+    const double2 zi = make_double2(i11 * ri.x + i12 * ri.y, i12 * ri.x + i22 * ri.y);
+    a.x[i] = xi;
+    a.r[i] = ri;
+    a.z[i] = zi;
+    acc[0] += ri.x * zi.x + ri.y * zi.y;
+  }
+  block_sum<1>(acc);
+  if (threadIdx.x == 0) a.part[(size_t)(1 + ((k + 1) & 1)) * a.n_tiles + t] = acc[0];
+}
+
+// Partials of ||b - C x||^2 (plain float64) into part[0 .. n_tiles).
+__global__ void __launch_bounds__(kCoupledBlock) k_cc_resid(CA a) {
+  int t, r0, r1;
+  tile_rows(a, t, r0, r1);
+  double acc[1] = {0.0};
+  for (int i = r0 + (int)threadIdx.x; i < r1; i += blockDim.x) {
+    double2 xn[3];
+#pragma unroll
+    for (int kk = 0; kk < 3; ++kk) {
+      const int o = a.nb[(size_t)kk * a.n + i];
+      xn[kk] = o >= 0 ? a.x[o] : make_double2(0.0, 0.0);
+    }
+    const double2 cx = apply_row(a, i, a.x[i], xn);
+    const double2 bi = a.b[i];
+    const double tx = bi.x - cx.x, ty = bi.y - cx.y;
+    acc[0] += tx * tx + ty * ty;
+  }
+  block_sum<1>(acc);
+  if (threadIdx.x == 0) a.part[t] = acc[0];
+}
+
+__global__ void k_cc_scatter(int n, const int* __restrict__ perm, const double2* __restrict__ x,
+                             double* __restrict__ u, double* __restrict__ v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int o = perm[i];
+  const double2 xi = x[i];
+  u[o] = xi.x;
+  v[o] = xi.y;
+}
+
+#define CC_HIP(expr)                                                               \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess) {                                                        \
+      set_error(PM_HIP_ERROR, std::string(#expr) + ": " + hipGetErrorString(e_));  \
+      return PM_HIP_ERROR;                                                         \
+    }                                                                              \
+  } while (0)
+
+// Copies the n_tiles partials at part and the flag to the host; returns
+// their fixed-order sum in *sum and the flag in *flag.
+int fetch_sum(const CA& a, double* h_part, hipStream_t s, double* sum, int32_t* flag) {
+  CC_HIP(hipMemcpyAsync(h_part, a.part, sizeof(double) * a.n_tiles, hipMemcpyDeviceToHost, s));
+  CC_HIP(hipMemcpyAsync(h_part + a.n_tiles, a.flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  CC_HIP(hipStreamSynchronize(s));
+  double acc = 0.0;
+  for (int t = 0; t < a.n_tiles; ++t) acc += h_part[t];
+  *sum = acc;
+  std::memcpy(flag, h_part + a.n_tiles, sizeof(int32_t));
+  return PM_OK;
+}
+
+}  // namespace
+
+int coupled_pcg(const CoupledIn& in, CoupledWork& w, double tol, int max_it, int check_every,
+                pm_info* info, hipStream_t s) {
+  CA a;
+  a.n = in.n;
+  a.tile_rows = w.tile_rows;
+  a.n_tiles = w.n_tiles;
+  a.nb = in.nb;
+  a.w = w.w;
+  a.dm = w.dm;
+  a.inv = w.inv;
+  a.b = w.b;
+  a.x = w.x;
+  a.r = w.r;
+  a.z = w.z;
+  a.q = w.q;
+  a.p0 = w.p[0];
+  a.p1 = w.p[1];
+  a.part = w.part;
+  a.scal = w.scal;
+  a.flag = w.flag;
+  const int grid = a.n_tiles;
+  CC_HIP(hipMemsetAsync(a.flag, 0, sizeof(int32_t), s));
+  k_cc_setup<<<grid, kCoupledBlock, 0, s>>>(a, in.perm, in.pos, in.diagpos, in.val_x, in.val_y,
+                                           in.mA, in.b_x, in.b_y);
+  CC_HIP(hipGetLastError());
+  double bb = 0.0;
+  int32_t flag = 0;
+  if (int r = fetch_sum(a, w.h_part, s, &bb, &flag)) return r;
+  if (flag) {
+    const int st = flag == kFlagNonfinite ? PM_NONFINITE : PM_INVALID_ARG;
+    set_error(st, flag == kFlagPattern
+                      ? "coupled CP1: the x and y matrices differ off the diagonal"
+                      : (flag == kFlagNotSpd ? "coupled CP1: a cell's 2x2 block is not positive "
+                                               "definite"
+                                             : "coupled CP1: non-finite right-hand side"));
+    return st;
+  }
+  pm_info res{};
+  res.bnorm = std::sqrt(bb);
+  int status = PM_OK;
+  int k = 0;
+  if (bb > 0.0) {
+    status = PM_MAXIT;
+    double rel = 1.0;  // x = 0
+    while (k < max_it) {
+      const int steps = std::min(check_every - k % check_every, max_it - k);
+      for (int j = 0; j < steps; ++j, ++k) {
+        k_cc_spmv<<<grid, kCoupledBlock, 0, s>>>(a, k);
+        k_cc_update<<<grid, kCoupledBlock, 0, s>>>(a, k);
+      }
+      CC_HIP(hipGetLastError());
+      k_cc_resid<<<grid, kCoupledBlock, 0, s>>>(a);
+      double r2 = 0.0;
+      if (int r = fetch_sum(a, w.h_part, s, &r2, &flag)) return r;
+      rel = std::sqrt(r2) / res.bnorm;
+      if (flag == kFlagBreakdown) {
+        status = PM_BREAKDOWN;
+        break;
+      }
+      if (rel <= tol) {
+        status = PM_OK;
+        break;
+      }
+    }
+    res.rel_res_true = rel;
+  }
+  k_cc_scatter<<<(a.n + 255) / 256, 256, 0, s>>>(a.n, in.perm, a.x, in.u, in.v);
+  CC_HIP(hipGetLastError());
+  CC_HIP(hipStreamSynchronize(s));
+  res.iters = k;
+  res.status = status;
+  if (info) *info = res;
+  return status;
+}
+
+}  // namespace pm

@@ -27,6 +27,7 @@
 #include <string>
 #include <vector>
 
+#include "coupled.h"
 #include "kernels.h"
 #include "pm_internal.h"
 #include "solver.h"
@@ -458,6 +459,9 @@ struct pm_mesh {
   pm_batch* pair = nullptr;
   double *pv = nullptr, *pb = nullptr, *px = nullptr, *pprev = nullptr;  // [2 nnz], [2n] x3
   double *mA = nullptr, *ppart = nullptr, *h_part = nullptr;           // [n], [blocks][4], pinned
+  // coupled CP1 conjugate gradients: workspace, created by the first call
+  CoupledWork cw;
+  bool cw_ready = false;
   // the solver workspace (a set with one system)
   SolveSet set;
   std::vector<void*> allocs;
@@ -486,6 +490,7 @@ void free_mesh(pm_mesh* m) {
   if (!m) return;
   if (m->pair) pm_batch_destroy(m->pair);
   if (m->h_part) (void)hipHostFree(m->h_part);
+  if (m->cw.h_part) (void)hipHostFree(m->cw.h_part);
   set_free(m->set);
   for (void* p : m->allocs) (void)hipFree(p);
   if (m->h_err) (void)hipHostFree(m->h_err);
@@ -875,7 +880,8 @@ int ensure_pair(pm_mesh* m) {
   int r = PM_OK;
   if ((r = dalloc(m, &m->pv, 2 * (size_t)m->nnz)) || (r = dalloc(m, &m->pb, 2 * n)) ||
       (r = dalloc(m, &m->px, 2 * n)) || (r = dalloc(m, &m->pprev, 2 * n)) ||
-      (r = dalloc(m, &m->mA, n)) || (r = dalloc(m, &m->ppart, 4 * (size_t)kChangeBlocks))) {
+      (!m->mA && (r = dalloc(m, &m->mA, n))) ||
+      (r = dalloc(m, &m->ppart, 4 * (size_t)kChangeBlocks))) {
     pm_batch_destroy(b);
     return r;
   }
@@ -887,6 +893,40 @@ int ensure_pair(pm_mesh* m) {
     return PM_HIP_ERROR;
   }
   m->pair = b;
+  return PM_OK;
+}
+
+// The coupled-CG workspace, on first use.
+int ensure_coupled(pm_mesh* m) {
+  if (m->cw_ready) return PM_OK;
+  CoupledWork& w = m->cw;
+  const size_t n = m->n;
+  w.tile_rows = kCoupledTile;
+  w.n_tiles = coupled_tiles(m->n);
+  double2* v2[7];
+  int r = PM_OK;
+  if ((!m->mA && (r = dalloc(m, &m->mA, n))) || (r = dalloc(m, &w.w, 3 * n)) ||
+      (r = dalloc(m, &w.dm, 3 * n)) || (r = dalloc(m, &w.inv, 3 * n)) ||
+      (r = dalloc(m, &w.part, 3 * (size_t)w.n_tiles)) || (r = dalloc(m, &w.scal, 2)) ||
+      (r = dalloc(m, &w.flag, 1)))
+    return r;
+  for (auto& p : v2)
+    if ((r = dalloc(m, &p, n))) return r;
+  w.b = v2[0];
+  w.x = v2[1];
+  w.r = v2[2];
+  w.z = v2[3];
+  w.q = v2[4];
+  w.p[0] = v2[5];
+  w.p[1] = v2[6];
+  hipError_t e = hipHostMalloc((void**)&w.h_part, sizeof(double) * (w.n_tiles + 1),
+                               hipHostMallocDefault);
+  if (e != hipSuccess) {
+    w.h_part = nullptr;
+    set_error(PM_HIP_ERROR, std::string("hipHostMalloc: ") + hipGetErrorString(e));
+    return PM_HIP_ERROR;
+  }
+  m->cw_ready = true;
   return PM_OK;
 }
 
@@ -985,6 +1025,51 @@ int cp1_solve_coupled(pm_mesh* m, const pm_cell_params* prm, double nu, double d
   if (st < 0) return st;
   if (st != PM_OK) return st;
   return met || max_outer == 0 ? PM_OK : PM_MAXIT;
+}
+
+int cp1_solve_coupled_pcg(pm_mesh* m, const pm_cell_params* prm, double nu, double dt,
+                          const double* val_x, const double* val_y, const double* b_x,
+                          const double* b_y, double* u, double* v, const pm_opts* opts,
+                          pm_info* info, hipStream_t s) {
+  if (!m || !prm || !prm->eps || !prm->logk || !val_x || !val_y || !b_x || !b_y || !u || !v ||
+      u == v || !(dt > 0.0) || !(nu >= 0.0) || !std::isfinite(nu) || !std::isfinite(dt)) {
+    set_error(PM_INVALID_ARG, "cp1_solve_coupled_pcg: invalid argument");
+    return PM_INVALID_ARG;
+  }
+  pm_opts o;
+  pm_opts_default(&o);
+  if (opts) o = *opts;
+  if (int r = check_opts(o)) return r;
+  if (o.precision != PM_FP64) {
+    set_error(PM_INVALID_ARG, "cp1_solve_coupled_pcg: float64 only");
+    return PM_INVALID_ARG;
+  }
+  if (int r = ensure_coupled(m)) return r;
+  PM_HIP(hipMemsetAsync(m->asm_err, 0, sizeof(int32_t), s));
+  k_cp1_mass<<<blocks_for(m->n, 256), 256, 0, s>>>(m->n, m->perm, prm->eps, prm->logk, prm->chi,
+                                                   prm->g11, prm->g12, prm->g22, nu, dt, m->area,
+                                                   m->mA, m->asm_err);
+  PM_HIP(hipGetLastError());
+  PM_HIP(hipMemcpyAsync(m->h_err, m->asm_err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  PM_HIP(hipStreamSynchronize(s));
+  if (*m->h_err) {
+    set_error(*m->h_err, "cp1_solve_coupled_pcg: invalid or non-finite cell parameters");
+    return *m->h_err;
+  }
+  CoupledIn in;
+  in.n = m->n;
+  in.perm = m->perm;
+  in.nb = m->nb;
+  in.pos = m->pos;
+  in.diagpos = m->diagpos;
+  in.val_x = val_x;
+  in.val_y = val_y;
+  in.mA = m->mA;
+  in.b_x = b_x;
+  in.b_y = b_y;
+  in.u = u;
+  in.v = v;
+  return coupled_pcg(in, m->cw, o.tol, o.max_it, o.replace_every, info, s);
 }
 
 int pm_time_cross(pm_mesh* m, const pm_cell_params* prm, double nu, double dt, const double* g,

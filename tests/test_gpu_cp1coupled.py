@@ -144,3 +144,112 @@ def test_pass_limits_and_statuses():
     # still usable, and a second call reuses the pair batch
     o, u, v, info = run_both(c, 1e-3)
     assert info["outer"] == o["outer"]
+
+
+# ---------------------------------------------------------------------------
+# Block-Jacobi CG on the coupled system (cp1_solve_coupled_pcg) against the
+# oracle's coupled_pcg: same algorithm and checks, so the same iteration
+# count; true residual <= 1e-10 (evaluated by the oracle) and 1e-9 relative
+# error.  The channel cases span several tiles of 4096 rows with a ragged
+# last tile.
+# ---------------------------------------------------------------------------
+
+
+@functools.lru_cache(maxsize=None)
+def chan_case(rows):
+    w = workloads.channel(rows, 3, aniso=True)
+    m = w["mesh"]
+    geo = geometry.build(m["xy"], m["tri"], w["side_tag"])
+    perm = ordering.rcm(geo["nbr"])
+    Ax = oasm.assemble(geo, perm, oasm.CP1X, w["params"], w["nu"], w["dt"])["A"]
+    Ay = oasm.assemble(geo, perm, oasm.CP1Y, w["params"], w["nu"], w["dt"])["A"]
+    mesh = B().Mesh(m["xy"], m["tri"], w["side_tag"])
+    dev = torch.device("cuda:0")
+    tprm = {k: torch.tensor(v, device=dev) for k, v in w["params"].items()}
+    vx = B().assemble_corrector(mesh, B().PM_CP1X, tprm, w["nu"], w["dt"])["val64"]
+    vy = B().assemble_corrector(mesh, B().PM_CP1Y, tprm, w["nu"], w["dt"])["val64"]
+    return {"geo": geo, "perm": perm, "prm": w["params"], "tprm": tprm, "dt": w["dt"], "Ax": Ax,
+            "Ay": Ay, "mesh": mesh, "vx": vx, "vy": vy, "bx": w["rhs"]["cp1x"],
+            "by": w["rhs"]["cp1y"], "dev": dev, "n": geo["n"]}
+
+
+def pcg_both(c, **kw):
+    perm = c["perm"]
+    m = occ.coupling_weights(c["geo"], c["prm"], NU, c["dt"])[perm]
+    (uo, vo), io = occ.coupled_pcg(c["Ax"], c["Ay"], m, c["bx"][perm], c["by"][perm],
+                                   tol=kw.get("tol", 1e-10), max_it=kw.get("max_it", 100000),
+                                   check_every=kw.get("replace_every", 50))
+    d = c["dev"]
+    u, v, info = B().cp1_solve_coupled_pcg(c["mesh"], c["tprm"], NU, c["dt"], c["vx"], c["vy"],
+                                           torch.tensor(c["bx"], device=d),
+                                           torch.tensor(c["by"], device=d), **kw)
+    return (to_cell(perm, uo), to_cell(perm, vo), io), (u.cpu().numpy(), v.cpu().numpy(), info), m
+
+
+@pytest.mark.parametrize("name", ["const_dir", "random_dir", "chan30", "chan60"])
+def test_coupled_pcg_matches_oracle(name):
+    c = chan_case(int(name[4:])) if name.startswith("chan") else case(name)
+    (uo, vo, io), (u, v, info), m = pcg_both(c)
+    perm = c["perm"]
+    assert info["status"] == 0 and io["status"] == 0
+    assert info["iters"] == io["iters"]
+    C = occ.coupled_matrix(c["Ax"], c["Ay"], m)
+    b = np.concatenate([c["bx"][perm], c["by"][perm]])
+    x = np.concatenate([u[perm], v[perm]])
+    res = np.linalg.norm(b - C @ x) / np.linalg.norm(b)
+    # both evaluate ||b - C x|| in float64: they agree to the rounding of C x
+    floor = 64 * 2.0 ** -53 * np.linalg.norm(abs(C) @ np.abs(x)) / np.linalg.norm(b)
+    assert res <= 1e-10 and abs(info["rel_res_true"] - res) <= 1e-3 * res + floor
+    xo = np.concatenate([uo, vo])
+    assert np.linalg.norm(np.concatenate([u, v]) - xo) <= 1e-9 * np.linalg.norm(xo)
+
+
+def test_coupled_pcg_limits_and_errors():
+    c = chan_case(30)
+    d = c["dev"]
+    bx, by = torch.tensor(c["bx"], device=d), torch.tensor(c["by"], device=d)
+    # iteration limit that is not a multiple of the check period
+    (uo, vo, io), (u, v, info), _ = pcg_both(c, max_it=73)
+    assert info["status"] == B().PM_MAXIT == io["status"] and info["iters"] == 73 == io["iters"]
+    assert abs(info["rel_res_true"] - io["rel_res_true"]) <= 1e-6 * io["rel_res_true"]
+    assert np.linalg.norm(u - uo) <= 1e-9 * np.linalg.norm(uo)
+    # zero right-hand side
+    z = torch.zeros_like(bx)
+    u0, v0, i0 = B().cp1_solve_coupled_pcg(c["mesh"], c["tprm"], NU, c["dt"], c["vx"], c["vy"], z, z)
+    assert i0["status"] == 0 and i0["iters"] == 0 and not u0.any() and not v0.any()
+    # errors: mixed precision, NaN right-hand side, off-diagonals that differ
+    with pytest.raises(B().PMError) as ei:
+        B().cp1_solve_coupled_pcg(c["mesh"], c["tprm"], NU, c["dt"], c["vx"], c["vy"], bx, by,
+                                  precision=1)
+    assert ei.value.status == B().PM_INVALID_ARG
+    bad = bx.clone()
+    bad[11] = float("nan")
+    with pytest.raises(B().PMError) as ei:
+        B().cp1_solve_coupled_pcg(c["mesh"], c["tprm"], NU, c["dt"], c["vx"], c["vy"], bad, by)
+    assert ei.value.status == B().PM_NONFINITE
+    _, rp, col = c["mesh"].export()
+    off = next(k for k in range(rp[0], rp[1]) if col[k] != 0)
+    vy2 = c["vy"].clone()
+    vy2[off] *= 1.5
+    with pytest.raises(B().PMError) as ei:
+        B().cp1_solve_coupled_pcg(c["mesh"], c["tprm"], NU, c["dt"], c["vx"], vy2, bx, by)
+    assert ei.value.status == B().PM_INVALID_ARG
+    # the mesh is still usable
+    (uo, vo, io), (u, v, info), _ = pcg_both(c)
+    assert info["status"] == 0 and info["iters"] == io["iters"]
+
+
+def test_coupled_pcg_is_the_limit_of_the_loop():
+    """The loop of App. B (cp1_solve_coupled) approaches the coupled CG
+    solution as the pass count grows (isotropic-free case, strong coupling)."""
+    c = case("const_dir")
+    d = c["dev"]
+    bx, by = torch.tensor(c["bx"], device=d), torch.tensor(c["by"], device=d)
+    uc, vc, ic = B().cp1_solve_coupled_pcg(c["mesh"], c["tprm"], NU, c["dt"], c["vx"], c["vy"], bx, by)
+    xc = torch.cat([uc, vc])
+    errs = []
+    for passes in (5, 20, 80):
+        u, v, _ = B().cp1_solve_coupled(c["mesh"], c["tprm"], NU, c["dt"], c["vx"], c["vy"], bx, by,
+                                        toll=0.0, max_outer=passes)
+        errs.append((torch.linalg.norm(torch.cat([u, v]) - xc) / torch.linalg.norm(xc)).item())
+    assert errs[0] > errs[1] > errs[2] and errs[2] < 1e-6

@@ -10,7 +10,8 @@ benchmark uses (tuned tile, block and schedule; default options).
     the residual property for float64 and mixed (an oracle solve at this size
     takes many minutes); the CP2 cross terms on every cell against the oracle
     and the residual property of the two-solve sequence; the systems of the
-    coupled CP1 loop's second pass under the oracle's matrices.
+    coupled CP1 loop's second pass under the oracle's matrices, and the
+    coupled CP1 solved by block-Jacobi CG to a true residual of 1e-10.
   * the 64-system log-normal batch (50k-500k triangles each) on the GPU; the
     residual property on eight systems under the oracle's matrices.
   * adjoint on the 1M channel (loss: squared misfit at 256 probe cells): the
@@ -194,6 +195,32 @@ def test_aniso_channel_4M_coupled_cp1():
     log(f"aniso 4M coupled CP1: err after 1 and 2 passes {runs[0][2]['err']:.3e} "
         f"{i2['err']:.3e}; pass-2 residuals {rx:.2e} {ry:.2e}")
     assert rx <= 1e-10 and ry <= 1e-10
+
+
+def test_aniso_channel_4M_coupled_cp1_pcg():
+    """Block-Jacobi CG on the coupled CP1 system of the 4M anisotropic channel:
+    true relative residual <= 1e-10 under the oracle's coupled matrix."""
+    from oracle import cp1coupled as occ
+
+    c = dict(channel_case(552, 3, True), key=(552, 3, True))
+    w = c["w"]
+    vx = B().assemble_corrector(c["mesh"], oasm.CP1X, c["prm"], w["nu"], w["dt"])["val64"]
+    vy = B().assemble_corrector(c["mesh"], oasm.CP1Y, c["prm"], w["nu"], w["dt"])["val64"]
+    bx, by = w["rhs"]["cp1x"], w["rhs"]["cp1y"]
+    u, v, info = B().cp1_solve_coupled_pcg(c["mesh"], c["prm"], w["nu"], w["dt"], vx, vy,
+                                           torch.tensor(bx, device=c["dev"]),
+                                           torch.tensor(by, device=c["dev"]))
+    perm = c["perm"]
+    Ax = oracle_system(552, 3, True, "cp1x")["A"]
+    Ay = oracle_system(552, 3, True, "cp1y")["A"]
+    m = occ.coupling_weights(c["geo"], w["params"], w["nu"], w["dt"])[perm]
+    C = occ.coupled_matrix(Ax, Ay, m)
+    b = np.concatenate([bx[perm], by[perm]])
+    x = np.concatenate([u.cpu().numpy()[perm], v.cpu().numpy()[perm]])
+    res = np.linalg.norm(b - C @ x) / np.linalg.norm(b)
+    log(f"aniso 4M coupled CP1 CG: {info['iters']} iterations, residual {res:.2e} "
+        f"(reported {info['rel_res_true']:.2e})")
+    assert info["status"] == 0 and res <= 1e-10
 
 
 @functools.lru_cache(maxsize=None)
