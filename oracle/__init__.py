@@ -24,6 +24,9 @@ Modules
   cp1coupled the x/y coupling of the CP1 through the anisotropic mass
              tensor and the paper's loop over the two scalar solves
              (Sec. 3.2.2, eq. cs1_sys2, eq. CS1_sys_coeff; App. B, eq. A1)
+  rt0        averaged side fluxes after CP1 (B_1 of CP2), the step's fluxes
+             and the RT0 velocity (eq. flux_k_+_2/3, eq. eta_flux; App. A,
+             eq. RT0)
 
 Parity status: every function above is pinned by tests/test_oracle_*.py
 against closed forms, invariants, special cases or brute force; none is
