@@ -13,7 +13,8 @@
  * GPU (single systems or batches of systems of uneven size), with a
  * hand-written adjoint for gradients with respect to the cell parameters and
  * the co-normal cross terms that form the right-hand side of the second CP2
- * solve, and the coupled anisotropic CP1.
+ * solve, the coupled anisotropic CP1, and the averaged side fluxes and RT0
+ * velocity around the CP2.
  *
  * Conventions shared by every entry point
  *   - Triangles are given counter-clockwise; side j of triangle e is the side
@@ -401,6 +402,50 @@ int cp1_solve_coupled_pcg(pm_mesh* mesh, const pm_cell_params* params, double nu
                           const double* val_x, const double* val_y, const double* b_x,
                           const double* b_y, double* u, double* v, const pm_opts* opts,
                           pm_info* info, hipStream_t stream);
+
+/*
+ * Side fluxes after CP1 (Sec. 3.2.2, eq. flux_k_+_2/3): for cell velocities
+ * (u, v), an interior side j of e carries the two cells' normal fluxes
+ * averaged with the other cell's area as weight,
+ *   fbar = (u_e . n_j A_ep + u_ep . n_j A_e) / (A_e + A_ep) l_j
+ * (n_j the outward normal of e), the same value with opposite sign from ep.
+ * A boundary side with the CP1 Dirichlet bit carries (g . n_j) l_j with g
+ * = (g_u, g_v) the prescribed velocity of that side; any other boundary side
+ * carries (u_e . n_j) l_j.  b1 = sum_j fbar_j is the CP2 source B_1 of
+ * eq. CS2_sys_coeff.
+ *   u, v        device [n_cells], cell order
+ *   g_u, g_v    device [n_cells][3], cell order, nullable (= 0)
+ *   fbar        device [n_cells][3] out, cell order
+ *   b1          device [n_cells] out, cell order, nullable
+ * Asynchronous on the stream; PM_INVALID_ARG for null arguments.
+ */
+int flux_average(pm_mesh* mesh, const double* u, const double* v, const double* g_u,
+                 const double* g_v, double* fbar, double* b1, hipStream_t stream);
+
+/*
+ * Velocity at the end of the step (Sec. 3.2.3, eq. eta_flux and the RT0
+ * reconstruction after it; App. A, eq. RT0).  Per side
+ *   Q_j = fbar_j + Fl_j^eta,
+ * Fl^eta the flux of Xi grad(eta): the two-point part of eta with the CP2
+ * matrix's weights (interior: w (eta_ep - eta_e); CP2 Dirichlet side:
+ * w_b (g - eta_e); Neumann: 0) plus the tangential cross term of eta~ (as in
+ * cp2_cross_rhs).  The cell sums of Q are the residual b_out - A eta of the
+ * second CP2 system, so they vanish when it is solved.  The velocity is the
+ * RT0 field u(x) = sum_j Q_j (x - x_j) / (2 A_e) (x_j the node opposite side
+ * j) at the centroid: its constant value when the sums vanish.
+ *   params .. g     as given to assemble_corrector for PM_CP2
+ *   eta_tilde, eta  device [n_cells], cell order: the two CP2 solutions
+ *   fbar            device [n_cells][3], cell order (flux_average)
+ *   u_out, v_out    device [n_cells] out, cell order
+ *   q_out           device [n_cells][3] out, cell order, nullable
+ * Errors: PM_INVALID_ARG, PM_NONFINITE (parameters, eta or eta~; reported
+ * after a stream sync).  Uses the mesh's workspace: calls on one mesh must
+ * not overlap in time.
+ */
+int rt0_update(pm_mesh* mesh, const pm_cell_params* params, double nu, double dt,
+               const double* g_dirichlet, const double* eta_tilde, const double* eta,
+               const double* fbar, double* u_out, double* v_out, double* q_out,
+               hipStream_t stream);
 
 /*
  * Measurement hook for cp2_cross_rhs: runs it n_launch times (after one

@@ -96,6 +96,8 @@ def lib():
             "cp1_solve_coupled": (C.c_int, [P, P, D, D, P, P, P, P, P, P, D, I32, P, P, P, P,
                                             P]),
             "cp1_solve_coupled_pcg": (C.c_int, [P, P, D, D, P, P, P, P, P, P, P, P, P]),
+            "flux_average": (C.c_int, [P, P, P, P, P, P, P, P]),
+            "rt0_update": (C.c_int, [P, P, D, D, P, P, P, P, P, P, P, P]),
         }
         for name, (res, args) in sig.items():
             if hasattr(L, name):
@@ -389,6 +391,31 @@ def cp1_solve_coupled_pcg(mesh: Mesh, params, nu, dt, val_x, val_y, b_x, b_y, st
     return u, v, info.as_dict()
 
 
+def flux_average(mesh: Mesh, u, v, g_u=None, g_v=None, stream=None):
+    """Returns (fbar [n, 3], b1 [n]) as device tensors, cell order."""
+    import torch
+
+    fbar = torch.empty((mesh.n, 3), dtype=torch.float64, device=u.device)
+    b1 = torch.empty_like(u)
+    _check(lib().flux_average(mesh.handle, _ptr(u), _ptr(v), _ptr(g_u), _ptr(g_v), _ptr(fbar),
+                              _ptr(b1), _stream(stream)))
+    return fbar, b1
+
+
+def rt0_update(mesh: Mesh, params, nu, dt, eta_tilde, eta, fbar, g_dirichlet=None, stream=None):
+    """Returns (u, v, Q [n, 3]) as device tensors, cell order."""
+    import torch
+
+    u = torch.empty_like(eta)
+    v = torch.empty_like(eta)
+    q = torch.empty((mesh.n, 3), dtype=torch.float64, device=eta.device)
+    p, _keep = _params(params)
+    _check(lib().rt0_update(mesh.handle, C.addressof(p), nu, dt, _ptr(g_dirichlet),
+                            _ptr(eta_tilde), _ptr(eta), _ptr(fbar), _ptr(u), _ptr(v), _ptr(q),
+                            _stream(stream)))
+    return u, v, q
+
+
 def pm_time_cross(mesh: Mesh, params, nu, dt, eta_tilde, b_in, n_launch: int, g_dirichlet=None,
                   stream=None):
     """Mean ms and bytes per launch of the three cross-term kernels."""
@@ -425,5 +452,6 @@ EXPORTED = [
     "pm_mesh_destroy", "pm_mesh_get_stats", "pm_mesh_export", "assemble_corrector", "pcg_solve",
     "pm_batch_create", "pm_batch_destroy", "pm_batch_offsets", "pcg_solve_batched", "pcg_adjoint",
     "pm_time_kernel", "pm_last_launch", "cp2_cross_rhs", "pm_time_cross",
-    "cp2_solve_two_step", "cp1_solve_coupled", "cp1_solve_coupled_pcg",
+    "cp2_solve_two_step", "cp1_solve_coupled", "cp1_solve_coupled_pcg", "flux_average",
+    "rt0_update",
 ]

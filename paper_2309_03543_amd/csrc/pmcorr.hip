@@ -364,6 +364,132 @@ k_cross_rhs(int n, const int* __restrict__ perm, const int* __restrict__ nb,
 }
 
 // ---------------------------------------------------------------------------
+// Averaged side fluxes after CP1 and the RT0 velocity at the end of the step
+// (Sec. 3.2.2, eq. flux_k_+_2/3; Sec. 3.2.3, eq. eta_flux; App. A, eq. RT0)
+// ---------------------------------------------------------------------------
+
+// Outward unit normal of the CCW side vector t.
+__device__ __forceinline__ void unit_normal(double tx, double ty, double& nx, double& ny,
+                                            double& l) {
+  l = sqrt(tx * tx + ty * ty);
+  nx = ty / l;
+  ny = -tx / l;
+}
+
+// fbar[e][k]: an interior side carries the two cells' normal fluxes averaged
+// with the other cell's area as weight, (u_e.n A_ep + u_ep.n A_e) / (A_e +
+// A_ep) l (n the outward normal of e); a side with a prescribed velocity (CP1
+// Dirichlet bit) carries (g.n) l, any other boundary side (u_e.n) l.  The
+// expression gives bitwise opposite values from the two cells.  b1[e] is the
+// sum of the three.
+__global__ void k_flux_avg(int n, const int* __restrict__ perm, const int* __restrict__ nb,
+                           const int8_t* __restrict__ tag, const double* __restrict__ tx,
+                           const double* __restrict__ ty, const double* __restrict__ area,
+                           const double* __restrict__ u, const double* __restrict__ v,
+                           const double* __restrict__ gu, const double* __restrict__ gv,
+                           double* __restrict__ fbar, double* __restrict__ b1) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int old = perm[i];
+  const double ue = u[old], ve = v[old], Ae = area[i];
+  double f[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const size_t s = (size_t)k * n + i;
+    double nx, ny, l;
+    unit_normal(tx[s], ty[s], nx, ny, l);
+    const double une = ue * nx + ve * ny;
+    const int o = nb[s];
+    if (o >= 0) {
+      const int oo = perm[o];
+      const double Ao = area[o];
+      const double unp = u[oo] * nx + v[oo] * ny;
+      f[k] = (une * Ao + unp * Ae) / (Ae + Ao) * l;
+    } else if (tag[s] & 1) {
+      const double gx = gu ? gu[3 * (size_t)old + k] : 0.0;
+      const double gy = gv ? gv[3 * (size_t)old + k] : 0.0;
+      f[k] = (gx * nx + gy * ny) * l;
+    } else {
+      f[k] = une * l;
+    }
+    fbar[3 * (size_t)old + k] = f[k];
+  }
+  if (b1) b1[old] = (f[0] + f[1]) + f[2];
+}
+
+// Renumbered copy of a cell-order vector.
+__global__ void k_gather(int n, const int* __restrict__ perm, const double* __restrict__ src,
+                         double* __restrict__ dst, int32_t* err) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double x = src[perm[i]];
+  if (!isfinite(x)) atomicExch(err, PM_NONFINITE);
+  dst[i] = x;
+}
+
+// Q = fbar + Fl^eta per side, with Fl^eta the two-point flux of eta (the
+// CP2 matrix weight times the difference; on a CP2 Dirichlet side the
+// boundary weight times g - eta) plus the tangential term of the cross
+// estimates F of eta~ (as in k_cross_rhs); then the RT0 field
+// u(x) = sum_k Q_k (x - x_k) / (2 A) at the centroid, where centroid - x_k
+// = (t_{k+2} - t_{k+1}) / 3 in side vectors.
+__global__ void __launch_bounds__(256)
+k_rt0(int n, const int* __restrict__ perm, const int* __restrict__ nb,
+      const int8_t* __restrict__ nbs, const int8_t* __restrict__ tag,
+      const uint8_t* __restrict__ avail, const double* __restrict__ T,
+      const double* __restrict__ tx, const double* __restrict__ ty,
+      const double* __restrict__ area, const double* __restrict__ X11,
+      const double* __restrict__ X12, const double* __restrict__ X22,
+      const double* __restrict__ eta_r, const double* __restrict__ F,
+      const double* __restrict__ g, const double* __restrict__ fbar,
+      double* __restrict__ u_out, double* __restrict__ v_out, double* __restrict__ q_out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int old = perm[i];
+  const unsigned av = avail[i];
+  const double e = eta_r[i];
+  const double x11 = X11[i], x12 = X12[i], x22 = X22[i];
+  double Q[3], sx[3], sy[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const size_t s = (size_t)k * n + i;
+    const int o = nb[s];
+    sx[k] = tx[s];
+    sy[k] = ty[s];
+    const bool mine = (av >> k) & 1u;
+    const double f = F[s];
+    double normal = 0.0, tang = 0.0;
+    if (o >= 0) {
+      const double a11 = 0.5 * (x11 + X11[o]);
+      const double a12 = 0.5 * (x12 + X12[o]);
+      const double a22 = 0.5 * (x22 + X22[o]);
+      const double w = T[s] * normal_quadratic(sx[k], sy[k], a11, a12, a22);
+      normal = w * (eta_r[o] - e);
+      const int kp = nbs[s];
+      const bool theirs = (avail[o] >> kp) & 1u;
+      const double fo = F[(size_t)kp * n + o];
+      tang = mine && theirs ? 0.5 * (f - fo) : (mine ? f : (theirs ? -fo : 0.0));
+    } else if (tag[s] & 2) {
+      const double w = T[s] * normal_quadratic(sx[k], sy[k], x11, x12, x22);
+      normal = w * ((g ? g[3 * (size_t)old + k] : 0.0) - e);
+      tang = mine ? f : 0.0;
+    }
+    Q[k] = (fbar[3 * (size_t)old + k] + normal) + tang;
+    if (q_out) q_out[3 * (size_t)old + k] = Q[k];
+  }
+  double ux = 0.0, uy = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int a = k == 2 ? 0 : k + 1, b = k == 0 ? 2 : k - 1;
+    ux += Q[k] * (sx[b] - sx[a]);
+    uy += Q[k] * (sy[b] - sy[a]);
+  }
+  const double c = 1.0 / (6.0 * area[i]);
+  u_out[old] = ux * c;
+  v_out[old] = uy * c;
+}
+
+// ---------------------------------------------------------------------------
 // Coupled CP1 (Sec. 3.2.2, eq. cs1_sys2 and eq. CS1_sys_coeff; App. B,
 // eq. A1): with anisotropic permeability M12 = nu eps Kfrak_12 couples the x
 // and y systems through the cell term M12 A_e.  The loop of App. B solves
@@ -454,6 +580,7 @@ struct pm_mesh {
   // CP2 cross-term workspace (renumbered order)
   double *eta_r = nullptr, *F = nullptr;  // [n], [3][n]
   double* b2 = nullptr;                   // [n] second right-hand side, cell order
+  double* eta2_r = nullptr;               // [n] renumbered eta for the RT0 update
   // coupled CP1: a two-system batch of this mesh (x, y) and its packed
   // vectors, created by the first cp1_solve_coupled call
   pm_batch* pair = nullptr;
@@ -651,6 +778,7 @@ int pm_mesh_create(int32_t n_nodes, const double* xy, int32_t n_cells, const int
   ALLOC(m->eta_r, n);
   ALLOC(m->F, 3 * n);
   ALLOC(m->b2, n);
+  ALLOC(m->eta2_r, n);
   ALLOC(m->T, 3 * n);
   ALLOC(m->tx, 3 * n);
   ALLOC(m->ty, 3 * n);
@@ -1070,6 +1198,47 @@ int cp1_solve_coupled_pcg(pm_mesh* m, const pm_cell_params* prm, double nu, doub
   in.u = u;
   in.v = v;
   return coupled_pcg(in, m->cw, o.tol, o.max_it, o.replace_every, info, s);
+}
+
+int flux_average(pm_mesh* m, const double* u, const double* v, const double* g_u,
+                 const double* g_v, double* fbar, double* b1, hipStream_t s) {
+  if (!m || !u || !v || !fbar) {
+    set_error(PM_INVALID_ARG, "flux_average: invalid argument");
+    return PM_INVALID_ARG;
+  }
+  k_flux_avg<<<blocks_for(m->n, 256), 256, 0, s>>>(m->n, m->perm, m->nb, m->tag, m->tx, m->ty,
+                                                   m->area, u, v, g_u, g_v, fbar, b1);
+  PM_HIP(hipGetLastError());
+  return PM_OK;
+}
+
+int rt0_update(pm_mesh* m, const pm_cell_params* prm, double nu, double dt, const double* g,
+               const double* eta_tilde, const double* eta, const double* fbar, double* u_out,
+               double* v_out, double* q_out, hipStream_t s) {
+  if (int r = cross_args_ok(m, prm, nu, dt, eta_tilde, fbar, u_out, "rt0_update")) return r;
+  if (!eta || !v_out || u_out == v_out) {
+    set_error(PM_INVALID_ARG, "rt0_update: invalid argument");
+    return PM_INVALID_ARG;
+  }
+  const int nbk = blocks_for(m->n, 256);
+  PM_HIP(hipMemsetAsync(m->asm_err, 0, sizeof(int32_t), s));
+  k_cross_prep<<<nbk, 256, 0, s>>>(m->n, m->perm, prm->eps, prm->logk, prm->chi, prm->g11,
+                                   prm->g12, prm->g22, nu, dt, eta_tilde, m->X11, m->X12, m->X22,
+                                   m->eta_r, m->asm_err);
+  k_cross_est<<<nbk, 256, 0, s>>>(m->n, m->perm, m->nb, m->tag, m->avail, m->T, m->tx, m->ty,
+                                  m->X11, m->X12, m->X22, m->eta_r, g, m->F);
+  k_gather<<<nbk, 256, 0, s>>>(m->n, m->perm, eta, m->eta2_r, m->asm_err);
+  k_rt0<<<nbk, 256, 0, s>>>(m->n, m->perm, m->nb, m->nbs, m->tag, m->avail, m->T, m->tx, m->ty,
+                            m->area, m->X11, m->X12, m->X22, m->eta2_r, m->F, g, fbar, u_out,
+                            v_out, q_out);
+  PM_HIP(hipGetLastError());
+  PM_HIP(hipMemcpyAsync(m->h_err, m->asm_err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  PM_HIP(hipStreamSynchronize(s));
+  if (*m->h_err) {
+    set_error(*m->h_err, "rt0_update: invalid or non-finite cell parameters, eta or eta~");
+    return *m->h_err;
+  }
+  return PM_OK;
 }
 
 int pm_time_cross(pm_mesh* m, const pm_cell_params* prm, double nu, double dt, const double* g,

@@ -11,7 +11,9 @@ benchmark uses (tuned tile, block and schedule; default options).
     takes many minutes); the CP2 cross terms on every cell against the oracle
     and the residual property of the two-solve sequence; the systems of the
     coupled CP1 loop's second pass under the oracle's matrices, and the
-    coupled CP1 solved by block-Jacobi CG to a true residual of 1e-10.
+    coupled CP1 solved by block-Jacobi CG to a true residual of 1e-10; the
+    whole step (coupled CP1, averaged fluxes, both CP2 solves, RT0) with
+    continuous fluxes whose cell sums are the CP2 residual.
   * the 64-system log-normal batch (50k-500k triangles each) on the GPU; the
     residual property on eight systems under the oracle's matrices.
   * adjoint on the 1M channel (loss: squared misfit at 256 probe cells): the
@@ -221,6 +223,22 @@ def test_aniso_channel_4M_coupled_cp1_pcg():
     log(f"aniso 4M coupled CP1 CG: {info['iters']} iterations, residual {res:.2e} "
         f"(reported {info['rel_res_true']:.2e})")
     assert info["status"] == 0 and res <= 1e-10
+
+
+def test_aniso_channel_4M_whole_step():
+    """Coupled CP1, averaged fluxes, the two CP2 solves and the RT0 velocity
+    on the 4M anisotropic channel, all on the GPU: the side fluxes are
+    continuous bitwise and their cell sums equal the second CP2 system's
+    residual under the oracle's matrix (below 1e-10 relative)."""
+    from test_gpu_rt0 import check_step, whole_step
+
+    c = channel_case(552, 3, True)
+    c = dict(c, tprm=c["prm"], n=c["geo"]["n"])
+    A = oracle_system(552, 3, True, "cp2")["A"]
+    out = whole_step(c)
+    rel = check_step(c, out, A)
+    log(f"aniso 4M whole step: |sum_j Q_j| / |b2| = {rel:.2e}, "
+        f"|u| max {np.abs(out['u2']).max():.3g}")
 
 
 @functools.lru_cache(maxsize=None)
