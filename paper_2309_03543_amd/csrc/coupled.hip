@@ -97,18 +97,17 @@ __device__ __forceinline__ void tile_rows(const CA& a, int& tile, int& r0, int& 
   r1 = min(a.n, r0 + a.tile_rows);
 }
 
-// (C y)_i for the cell pair y (both components of every cell)
+// (C y)_i for the cell pair y (both components of every cell).  The weight
+// of a missing neighbour is stored as 0 and its y_nb entry is any finite
+// value, so the term vanishes exactly without a branch.
 __device__ __forceinline__ double2 apply_row(const CA& a, int i, double2 yi, const double2* y_nb) {
   const double dx = a.dm[i], dy = a.dm[(size_t)a.n + i], m = a.dm[2 * (size_t)a.n + i];
   double qx = dx * yi.x + m * yi.y, qy = m * yi.x + dy * yi.y;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    const size_t s = (size_t)k * a.n + i;
-    if (a.nb[s] >= 0) {
-      const double wk = a.w[s];
-      qx -= wk * y_nb[k].x;
-      qy -= wk * y_nb[k].y;
-    }
+    const double wk = a.w[(size_t)k * a.n + i];
+    qx -= wk * y_nb[k].x;
+    qy -= wk * y_nb[k].y;
   }
   return make_double2(qx, qy);
 }
@@ -161,6 +160,12 @@ k_cc_setup(CA a, const int* __restrict__ perm, const int* __restrict__ pos,
   }
 }
 
+// Two rows per trip: the neighbour indices of both rows are loaded first, then
+// every gather of both rows is issued with clamped (always valid) addresses
+// before any value is used, so the loads overlap; rows past the tile and
+// missing neighbours are masked only when the products are formed.
+constexpr int kSpmvRows = 2;
+
 __global__ void __launch_bounds__(kCoupledBlock) k_cc_spmv(CA a, int k) {
   if (*a.flag) return;
   const double rz = sum_tiles(a.part + (size_t)(1 + (k & 1)) * a.n_tiles, a.n_tiles);
@@ -171,32 +176,44 @@ __global__ void __launch_bounds__(kCoupledBlock) k_cc_spmv(CA a, int k) {
   int t, r0, r1;
   tile_rows(a, t, r0, r1);
   double acc[1] = {0.0};
-  for (int i = r0 + (int)threadIdx.x; i < r1; i += blockDim.x) {
-    double2 pn[3];
+  for (int base = r0 + (int)threadIdx.x; base < r1; base += kSpmvRows * blockDim.x) {
+    int row[kSpmvRows], nbo[kSpmvRows][3];
 #pragma unroll
-    for (int kk = 0; kk < 3; ++kk) {
-      const int o = a.nb[(size_t)kk * a.n + i];
-      pn[kk] = make_double2(0.0, 0.0);
-      if (o >= 0) {
-        const double2 zo = a.z[o];
-        if (k == 0) {
-          pn[kk] = zo;
-        } else {
-          const double2 po = pold[o];
-          pn[kk] = make_double2(zo.x + beta * po.x, zo.y + beta * po.y);
-        }
+    for (int r = 0; r < kSpmvRows; ++r) {
+      const int ir = base + r * (int)blockDim.x;
+      row[r] = ir < r1 ? ir : base;
+#pragma unroll
+      for (int kk = 0; kk < 3; ++kk) nbo[r][kk] = a.nb[(size_t)kk * a.n + row[r]];
+    }
+    double2 zn[kSpmvRows][3], pn_old[kSpmvRows][3], zi[kSpmvRows], pi_old[kSpmvRows];
+#pragma unroll
+    for (int r = 0; r < kSpmvRows; ++r) {
+      zi[r] = a.z[row[r]];
+      pi_old[r] = pold[row[r]];
+#pragma unroll
+      for (int kk = 0; kk < 3; ++kk) {
+        const int o = nbo[r][kk] >= 0 ? nbo[r][kk] : row[r];
+        zn[r][kk] = a.z[o];
+        pn_old[r][kk] = pold[o];
       }
     }
-    const double2 zi = a.z[i];
-    double2 pi = zi;
-    if (k != 0) {
-      const double2 po = pold[i];
-      pi = make_double2(zi.x + beta * po.x, zi.y + beta * po.y);
+#pragma unroll
+    for (int r = 0; r < kSpmvRows; ++r) {
+      if (base + r * (int)blockDim.x >= r1) continue;
+      const int i = row[r];
+      double2 pn[3];
+#pragma unroll
+      for (int kk = 0; kk < 3; ++kk) {
+        const double2 zo = zn[r][kk], po = pn_old[r][kk];
+        pn[kk] = k == 0 ? zo : make_double2(zo.x + beta * po.x, zo.y + beta * po.y);
+      }
+      double2 pi = zi[r];
+      if (k != 0) pi = make_double2(zi[r].x + beta * pi_old[r].x, zi[r].y + beta * pi_old[r].y);
+      pnew[i] = pi;
+      const double2 qi = apply_row(a, i, pi, pn);
+      a.q[i] = qi;
+      acc[0] += pi.x * qi.x + pi.y * qi.y;
     }
-    pnew[i] = pi;
-    const double2 qi = apply_row(a, i, pi, pn);
-    a.q[i] = qi;
-    acc[0] += pi.x * qi.x + pi.y * qi.y;
   }
   block_sum<1>(acc);
   if (threadIdx.x == 0) a.part[t] = acc[0];
