@@ -27,6 +27,8 @@ Modules
   rt0        averaged side fluxes after CP1 (B_1 of CP2), the step's fluxes
              and the RT0 velocity (eq. flux_k_+_2/3, eq. eta_flux; App. A,
              eq. RT0)
+  ic0        incomplete Cholesky with no fill, the paper's preconditioner,
+             for iteration-count context only (Sec. 3.2.2, 3.2.3)
 
 Parity status: every function above is pinned by tests/test_oracle_*.py
 against closed forms, invariants, special cases or brute force; none is

@@ -51,7 +51,7 @@ import numpy as np
 import scipy.linalg as sla
 
 OK, MAXIT, STAGNATED, BREAKDOWN = 0, 1, 2, -6
-JACOBI, CHEBYSHEV = 0, 1
+JACOBI, CHEBYSHEV, IC0 = 0, 1, 2
 CHEB_LMAX = 2.0
 CHEB_RATIO = 30.0
 
@@ -112,10 +112,12 @@ def true_residual(A, b, x, x_lo=None) -> np.ndarray:
 
 
 def pcg(A, b, tol=1e-10, max_it=100000, replace_every=50, x0=None, record=False,
-        stag_checks=40, precond=JACOBI, degree=4) -> tuple:
+        stag_checks=40, precond=JACOBI, degree=4, factor=None) -> tuple:
     """PCG with group-update residual replacement every `replace_every`
     iterations; returns (x, info) with info = iters, status, rel_res_true.
-    precond JACOBI: z = D^-1 r; CHEBYSHEV: z = chebyshev_apply(..., degree)."""
+    precond JACOBI: z = D^-1 r; CHEBYSHEV: z = chebyshev_apply(..., degree);
+    IC0: z = (L L^T)^-1 r with L = factor, or the IC(0) factor of A (the
+    paper's preconditioner; CPU reference only)."""
     b = np.asarray(b, np.float64)
     n = b.shape[0]
     x = np.zeros(n) if x0 is None else np.array(x0, np.float64)
@@ -131,6 +133,12 @@ def pcg(A, b, tol=1e-10, max_it=100000, replace_every=50, x0=None, record=False,
 
         def prec(v):
             return chebyshev_apply(A, dinv, v, degree)
+    elif precond == IC0:
+        from . import ic0 as _ic0
+        L = _ic0.ic0(A) if factor is None else factor
+
+        def prec(v):
+            return _ic0.ic0_apply(L, v)
     else:
         def prec(v):
             return dinv * v
