@@ -220,6 +220,28 @@ def main():
         med = float(np.median(times))
         solve_only = {"system": key, "ms_median": med, "solves_per_s": 1e3 / med,
                       "iters": info["iters"], "reps": len(times)}
+        # the same solve with the Chebyshev-polynomial preconditioner (degree
+        # 6), float64 and mixed: fewer, costlier iterations
+        cheb = {}
+        for prec in (0, 1):
+            B.pcg_solve(mesh0, val, rhs[0][key], precision=prec, precond=1, cheb_degree=6)
+            times = []
+            for _ in range(3):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                _, ic = B.pcg_solve(mesh0, val, rhs[0][key], precision=prec, precond=1,
+                                    cheb_degree=6)
+                e1.record()
+                e1.synchronize()
+                times.append(e0.elapsed_time(e1))
+            cheb["f64" if prec == 0 else "mixed"] = {
+                "ms_median": float(np.median(times)), "iters": ic["iters"],
+                "rel_res_true": ic["rel_res_true"], "status": ic["status"]}
+        solve_only["chebyshev_degree6"] = cheb
+        B.pcg_solve(mesh0, val, rhs[0][key])  # the kernel timing below uses the last solve's state
+        log(f"  {key} solve: Jacobi {med:.1f} ms ({info['iters']} it); Chebyshev-6 "
+            f"{cheb['f64']['ms_median']:.1f} ms ({cheb['f64']['iters']} it), mixed "
+            f"{cheb['mixed']['ms_median']:.1f} ms")
     # per-kernel timing on the state of the last solve of the step
     tmesh = mesh0 if batch is None else None
     kern = {}
