@@ -31,6 +31,33 @@ def test_library_exports_every_declared_symbol():
     assert sorted(B.EXPORTED) == names
 
 
+def declared_arity():
+    """Parameter count of every function the headers declare."""
+    out = {}
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", fn)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b([a-z_][a-z0-9_]*)\s*\(([^)]*)\)\s*;",
+                                 src, flags=re.M):
+                args = m.group(2).strip()
+                out[m.group(1)] = 0 if args in ("", "void") else args.count(",") + 1
+    return out
+
+
+def test_binding_signatures_match_the_header():
+    """The binding declares as many ctypes arguments as the header has
+    parameters, for every function (a mismatch would shift arguments)."""
+    B.lib()
+    ar = declared_arity()
+    assert set(ar) == set(declared_symbols())
+    lib = B.lib()
+    for name, n in ar.items():
+        f = getattr(lib, name)
+        assert f.argtypes is not None, name
+        assert len(f.argtypes) == n, (name, len(f.argtypes), n)
+
+
 def test_status_strings():
     assert B.status_string(0) == "ok"
     assert B.status_string(B.PM_NOT_DELAUNAY) == "mesh not Delaunay"
