@@ -343,6 +343,15 @@ def main():
         wallp = time.perf_counter() - t
         log(f"  coupled CP1 by block-Jacobi CG: {ip['iters']} iterations, {wallp * 1e3:.1f} ms, "
             f"residual {ip['rel_res_true']:.2e}")
+        B.cp1_solve_coupled_pcg(mesh0, prm0, w0["nu"], w0["dt"], vx, vy, bx, by, precision=1)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, _, ipm = B.cp1_solve_coupled_pcg(mesh0, prm0, w0["nu"], w0["dt"], vx, vy, bx, by,
+                                            precision=1)
+        torch.cuda.synchronize()
+        wallpm = time.perf_counter() - t
+        log(f"  coupled CP1 by block-Jacobi CG, mixed: {ipm['iters']} iterations, "
+            f"{wallpm * 1e3:.1f} ms, residual {ipm['rel_res_true']:.2e}")
         # the rest of the step around the CP2: averaged fluxes of the CP1
         # velocity, and the RT0 velocity from the two CP2 solutions above
         uc, vc, _ = B.cp1_solve_coupled_pcg(mesh0, prm0, w0["nu"], w0["dt"], vx, vy, bx, by)
@@ -366,6 +375,9 @@ def main():
                 "iters": [ic["x"]["iters"], ic["y"]["iters"]], "status": ic["status"],
                 "coupled_cg": {"ms": wallp * 1e3, "iters": ip["iters"], "status": ip["status"],
                                "rel_res_true": ip["rel_res_true"]},
+                "coupled_cg_mixed": {"ms": wallpm * 1e3, "iters": ipm["iters"],
+                                     "status": ipm["status"],
+                                     "rel_res_true": ipm["rel_res_true"]},
                 "step_tail": tail}
         log(f"  coupled CP1: {ic['outer']} passes, iterations {cp1c['iters']}, {wallc * 1e3:.1f} ms")
 

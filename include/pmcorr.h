@@ -383,20 +383,27 @@ int cp1_solve_coupled(pm_mesh* mesh, const pm_cell_params* params, double nu, do
  * times A_e, plus the Dirichlet terms), and one solve reaches the limit of
  * that iteration.  Starting from zero, every opts.replace_every iterations
  * the true residual ||b - C x||_2 (float64) is evaluated and the solve stops
- * once it is <= opts.tol ||b||_2; the recursive residual is not replaced.
+ * once it is <= opts.tol ||b||_2.  PM_FP64: every value is float64 and the
+ * recursive residual is not replaced.  PM_MIXED: the Krylov vectors and the
+ * per-iteration copies of the weights, diagonal blocks and block inverses are
+ * stored in float32 (arithmetic in float64); x, b and the residual check stay
+ * float64, and every check replaces the recursive residual by the true one
+ * (the direction restarts when the replaced r.z exceeds the recursive one a
+ * hundredfold).
  *   params, nu, dt  as given to assemble_corrector (for m)
  *   val_x, val_y    device [nnz]: the PM_CP1X and PM_CP1Y matrices; their
  *                   off-diagonals must agree (both are -nu T)
  *   b_x, b_y        device [n_cells], cell order (Dirichlet lifts included)
  *   u, v            device [n_cells] out, cell order; distinct
- *   opts            tol, max_it and replace_every apply; precision must be
- *                   PM_FP64; the other fields are ignored
+ *   opts            tol, max_it, replace_every and precision apply; the other
+ *                   fields are ignored
  *   info            host out, nullable: iterations, status, the true
  *                   relative residual of (u, v) and ||b||
  * Errors: PM_INVALID_ARG (arguments, off-diagonals that differ, a cell
  * block that is not positive definite), PM_NONFINITE, PM_BREAKDOWN.  The
- * first call on a mesh allocates a workspace of 23 n doubles, kept until
- * pm_mesh_destroy.
+ * first call on a mesh allocates a workspace of 13 n doubles, and the first
+ * call of each precision 13 n doubles (float64) or 19 n floats (mixed) more,
+ * kept until pm_mesh_destroy.
  */
 int cp1_solve_coupled_pcg(pm_mesh* mesh, const pm_cell_params* params, double nu, double dt,
                           const double* val_x, const double* val_y, const double* b_x,

@@ -26,18 +26,26 @@ struct CoupledIn {
   double* v = nullptr;
 };
 
-// Workspace (device unless noted), sized by coupled_work_doubles.
+// Workspace (device unless noted).  The float64 matrix copies, b, x and the
+// partials serve both precisions; each precision has its own vectors (and,
+// in mixed precision, float32 matrix copies), created on first use.
 struct CoupledWork {
   int tile_rows = 0, n_tiles = 0;
-  double* w = nullptr;     // [3][n] off-diagonal magnitudes (shared by x and y)
-  double* dm = nullptr;    // [3][n] diagonal of x, diagonal of y, coupling m
-  double* inv = nullptr;   // [3][n] inverse of each cell's 2x2 block
-  double2 *b = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *q = nullptr;
+  double* w64 = nullptr;    // [3][n] off-diagonal magnitudes (shared by x and y)
+  double* dm64 = nullptr;   // [3][n] diagonal of x, diagonal of y, coupling m
+  double* inv64 = nullptr;  // [3][n] inverse of each cell's 2x2 block
+  double2 *b = nullptr, *x = nullptr;
+  double2 *r = nullptr, *z = nullptr, *q = nullptr;  // float64 vectors
   double2* p[2] = {nullptr, nullptr};
-  double* part = nullptr;   // [3][n_tiles]: p.q, and r.z of even and odd iterations
+  float *w32 = nullptr, *dm32 = nullptr, *inv32 = nullptr;  // mixed precision
+  float2 *r32 = nullptr, *z32 = nullptr, *q32 = nullptr;
+  float2* p32[2] = {nullptr, nullptr};
+  double* part = nullptr;   // [4][n_tiles]: p.q (or the setup / residual sums), r.z of even
+                            // and odd iterations, r.z of a replaced residual
   double* scal = nullptr;   // [2]: r.z of even and odd iterations
   int32_t* flag = nullptr;  // [1]
   double* h_part = nullptr; // pinned host [n_tiles + 1]
+  bool ready = false, ready64 = false, ready32 = false;
 };
 
 constexpr int kCoupledTile = 4096;
@@ -45,8 +53,9 @@ constexpr int kCoupledBlock = 512;
 
 inline int coupled_tiles(int n) { return (n + kCoupledTile - 1) / kCoupledTile; }
 
-// Solves; tol, max_it, check_every as in pm_opts (tol, max_it, replace_every).
-int coupled_pcg(const CoupledIn& in, CoupledWork& w, double tol, int max_it, int check_every,
-                pm_info* info, hipStream_t s);
+// Solves; tol, max_it, check_every as in pm_opts (tol, max_it,
+// replace_every); precision PM_FP64 or PM_MIXED (its arrays must exist).
+int coupled_pcg(const CoupledIn& in, CoupledWork& w, int precision, double tol, int max_it,
+                int check_every, pm_info* info, hipStream_t s);
 
 }  // namespace pm

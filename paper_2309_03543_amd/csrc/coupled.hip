@@ -19,8 +19,18 @@
 //                q = C p; partial p.q
 //   k_cc_update  alpha = r.z / p.q; x += alpha p; r -= alpha q; z = P^{-1} r;
 //                partial r.z
-// Every check_every iterations the true residual ||b - C x|| decides the stop
-// (the recursive residual is not replaced).
+// Every check_every iterations the true residual ||b - C x|| decides the stop.
+//
+// Precisions.  In float64 every vector and matrix value is float64 and the
+// recursive residual is never replaced.  In mixed precision the Krylov
+// vectors (r, z, p, q) and the per-iteration copies of the weights, diagonal
+// blocks and block inverses are stored in float32 (all arithmetic in
+// float64); x, b and float64 copies of the matrix stay, and every check
+// replaces r by the float64 true residual b - C x, keeping the direction
+// unless the replaced r.z exceeds the recursive one a hundredfold (then the
+// next direction restarts, beta = 0).  A value rounded to float32 is rounded
+// once, when it is stored; a neighbour's new direction is recomputed and
+// rounded the same way as its owner stores it.
 //
 // Compiled with -ffp-contract=off.
 #include <hip/hip_runtime.h>
@@ -44,23 +54,53 @@ constexpr int kFlagNotSpd = 2;     // a cell's 2x2 block is not positive definit
 constexpr int kFlagNonfinite = 3;  // NaN or Inf in the right-hand side
 constexpr int kFlagBreakdown = 4;  // p.q <= 0 or not finite
 
+template <typename T>
+struct Pair;
+template <>
+struct Pair<double> {
+  using type = double2;
+};
+template <>
+struct Pair<float> {
+  using type = float2;
+};
+
+// T: storage type of the Krylov vectors and of the per-iteration matrix data.
+template <typename T>
 struct CA {
+  using V2 = typename Pair<T>::type;
   int n, tile_rows, n_tiles;
   const int* nb;
-  double* w;
-  double* dm;
-  double* inv;
+  T* w;            // [3][n] off-diagonal magnitudes
+  T* dm;           // [3][n] diagonal of x, diagonal of y, coupling m
+  T* inv;          // [3][n] block inverses
+  double* w64;     // float64 weights and blocks for the true residual
+  double* dm64;    // (the same arrays as w, dm in float64)
   double2* b;
   double2* x;
-  double2* r;
-  double2* z;
-  double2* q;
-  double2* p0;
-  double2* p1;
-  double* part;  // [3][n_tiles]: p.q (or the setup / residual sums), r.z even, r.z odd
+  V2* r;
+  V2* z;
+  V2* q;
+  V2* p0;
+  V2* p1;
+  double* part;  // [4][n_tiles]: p.q (or the setup / residual sums), r.z even, r.z odd,
+                 // r.z of a replaced residual
   double* scal;  // r.z of even and odd iterations
   int32_t* flag;
 };
+
+__device__ __forceinline__ double2 wide(double2 v) { return v; }
+__device__ __forceinline__ double2 wide(float2 v) { return make_double2(v.x, v.y); }
+template <typename V2>
+__device__ __forceinline__ V2 narrow(double x, double y);
+template <>
+__device__ __forceinline__ double2 narrow<double2>(double x, double y) {
+  return make_double2(x, y);
+}
+template <>
+__device__ __forceinline__ float2 narrow<float2>(double x, double y) {
+  return make_float2((float)x, (float)y);
+}
 
 // Fixed-order block sum of NV values; every thread gets the totals.
 template <int NV>
@@ -91,32 +131,38 @@ __device__ __forceinline__ double sum_tiles(const double* __restrict__ part, int
   return v[0];
 }
 
-__device__ __forceinline__ void tile_rows(const CA& a, int& tile, int& r0, int& r1) {
+template <typename T>
+__device__ __forceinline__ void tile_rows(const CA<T>& a, int& tile, int& r0, int& r1) {
   tile = xcd_block(blockIdx.x, gridDim.x);
   r0 = tile * a.tile_rows;
   r1 = min(a.n, r0 + a.tile_rows);
 }
 
-// (C y)_i for the cell pair y (both components of every cell).  The weight
-// of a missing neighbour is stored as 0 and its y_nb entry is any finite
-// value, so the term vanishes exactly without a branch.
-__device__ __forceinline__ double2 apply_row(const CA& a, int i, double2 yi, const double2* y_nb) {
-  const double dx = a.dm[i], dy = a.dm[(size_t)a.n + i], m = a.dm[2 * (size_t)a.n + i];
+// (C y)_i for the cell pair y (both components of every cell), with the
+// weights and blocks W / D (stored as T or as float64).  The weight of a
+// missing neighbour is stored as 0 and its y_nb entry is any finite value, so
+// the term vanishes exactly without a branch.
+template <typename W>
+__device__ __forceinline__ double2 apply_row(const W* __restrict__ w, const W* __restrict__ dm,
+                                             int n, int i, double2 yi, const double2* y_nb) {
+  const double dx = dm[i], dy = dm[(size_t)n + i], m = dm[2 * (size_t)n + i];
   double qx = dx * yi.x + m * yi.y, qy = m * yi.x + dy * yi.y;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    const double wk = a.w[(size_t)k * a.n + i];
+    const double wk = w[(size_t)k * n + i];
     qx -= wk * y_nb[k].x;
     qy -= wk * y_nb[k].y;
   }
   return make_double2(qx, qy);
 }
 
+template <typename T>
 __global__ void __launch_bounds__(kCoupledBlock)
-k_cc_setup(CA a, const int* __restrict__ perm, const int* __restrict__ pos,
+k_cc_setup(CA<T> a, const int* __restrict__ perm, const int* __restrict__ pos,
            const int* __restrict__ diagpos, const double* __restrict__ val_x,
            const double* __restrict__ val_y, const double* __restrict__ mA,
            const double* __restrict__ bx, const double* __restrict__ by) {
+  using V2 = typename CA<T>::V2;
   int t, r0, r1;
   tile_rows(a, t, r0, r1);
   double acc[2] = {0.0, 0.0};
@@ -131,31 +177,38 @@ k_cc_setup(CA a, const int* __restrict__ perm, const int* __restrict__ pos,
         wk = -val_x[ps];
         if (val_y[ps] != val_x[ps]) atomicExch(a.flag, kFlagPattern);
       }
-      a.w[s] = wk;
+      a.w64[s] = wk;
+      a.w[s] = (T)wk;
     }
     const double dx = val_x[diagpos[i]], dy = val_y[diagpos[i]], m = mA[o];
-    a.dm[i] = dx;
-    a.dm[(size_t)a.n + i] = dy;
-    a.dm[2 * (size_t)a.n + i] = m;
+    a.dm64[i] = dx;
+    a.dm64[(size_t)a.n + i] = dy;
+    a.dm64[2 * (size_t)a.n + i] = m;
+    a.dm[i] = (T)dx;
+    a.dm[(size_t)a.n + i] = (T)dy;
+    a.dm[2 * (size_t)a.n + i] = (T)m;
     const double det = dx * dy - m * m;
     if (!(dx > 0.0) || !(det > 0.0) || !isfinite(det)) atomicExch(a.flag, kFlagNotSpd);
-    const double i11 = dy / det, i12 = -m / det, i22 = dx / det;
+    const T i11 = (T)(dy / det), i12 = (T)(-m / det), i22 = (T)(dx / det);
     a.inv[i] = i11;
     a.inv[(size_t)a.n + i] = i12;
     a.inv[2 * (size_t)a.n + i] = i22;
     const double2 bb = make_double2(bx[o], by[o]);
     if (!isfinite(bb.x) || !isfinite(bb.y)) atomicExch(a.flag, kFlagNonfinite);
-    const double2 zz = make_double2(i11 * bb.x + i12 * bb.y, i12 * bb.x + i22 * bb.y);
+    const double2 rr = wide(narrow<V2>(bb.x, bb.y));
+    const V2 zs = narrow<V2>((double)i11 * rr.x + (double)i12 * rr.y,
+                             (double)i12 * rr.x + (double)i22 * rr.y);
+    const double2 zz = wide(zs);
     a.b[i] = bb;
     a.x[i] = make_double2(0.0, 0.0);
-    a.r[i] = bb;
-    a.z[i] = zz;
+    a.r[i] = narrow<V2>(rr.x, rr.y);
+    a.z[i] = zs;
     acc[0] += bb.x * bb.x + bb.y * bb.y;
-    acc[1] += bb.x * zz.x + bb.y * zz.y;
+    acc[1] += rr.x * zz.x + rr.y * zz.y;
   }
   block_sum<2>(acc);
   if (threadIdx.x == 0) {
-    a.part[t] = acc[0];                   // ||b||^2
+    a.part[t] = acc[0];                      // ||b||^2
     a.part[(size_t)a.n_tiles + t] = acc[1];  // r.z of iteration 0
   }
 }
@@ -164,15 +217,27 @@ k_cc_setup(CA a, const int* __restrict__ perm, const int* __restrict__ pos,
 // every gather of both rows is issued with clamped (always valid) addresses
 // before any value is used, so the loads overlap; rows past the tile and
 // missing neighbours are masked only when the products are formed.
+// After a replacement (replaced != 0) r.z comes from the replaced residual's
+// partials, and the direction restarts when it exceeds the recursive r.z a
+// hundredfold.
 constexpr int kSpmvRows = 2;
 
-__global__ void __launch_bounds__(kCoupledBlock) k_cc_spmv(CA a, int k) {
+template <typename T>
+__global__ void __launch_bounds__(kCoupledBlock) k_cc_spmv(CA<T> a, int k, int replaced) {
+  using V2 = typename CA<T>::V2;
   if (*a.flag) return;
-  const double rz = sum_tiles(a.part + (size_t)(1 + (k & 1)) * a.n_tiles, a.n_tiles);
+  const double rz_rec = sum_tiles(a.part + (size_t)(1 + (k & 1)) * a.n_tiles, a.n_tiles);
+  double rz = rz_rec;
+  bool restart = false;
+  if (replaced) {
+    rz = sum_tiles(a.part + 3 * (size_t)a.n_tiles, a.n_tiles);
+    restart = rz > 100.0 * rz_rec;
+  }
   if (blockIdx.x == 0 && threadIdx.x == 0) a.scal[k & 1] = rz;
-  const double beta = k == 0 ? 0.0 : rz / a.scal[(k - 1) & 1];
-  const double2* __restrict__ pold = (k & 1) ? a.p0 : a.p1;
-  double2* __restrict__ pnew = (k & 1) ? a.p1 : a.p0;
+  const double beta = (k == 0 || restart) ? 0.0 : rz / a.scal[(k - 1) & 1];
+  const V2* __restrict__ pold = (k & 1) ? a.p0 : a.p1;
+  V2* __restrict__ pnew = (k & 1) ? a.p1 : a.p0;
+  const bool fresh = k == 0 || restart;
   int t, r0, r1;
   tile_rows(a, t, r0, r1);
   double acc[1] = {0.0};
@@ -185,7 +250,7 @@ __global__ void __launch_bounds__(kCoupledBlock) k_cc_spmv(CA a, int k) {
 #pragma unroll
       for (int kk = 0; kk < 3; ++kk) nbo[r][kk] = a.nb[(size_t)kk * a.n + row[r]];
     }
-    double2 zn[kSpmvRows][3], pn_old[kSpmvRows][3], zi[kSpmvRows], pi_old[kSpmvRows];
+    V2 zn[kSpmvRows][3], pn_old[kSpmvRows][3], zi[kSpmvRows], pi_old[kSpmvRows];
 #pragma unroll
     for (int r = 0; r < kSpmvRows; ++r) {
       zi[r] = a.z[row[r]];
@@ -204,22 +269,31 @@ __global__ void __launch_bounds__(kCoupledBlock) k_cc_spmv(CA a, int k) {
       double2 pn[3];
 #pragma unroll
       for (int kk = 0; kk < 3; ++kk) {
-        const double2 zo = zn[r][kk], po = pn_old[r][kk];
-        pn[kk] = k == 0 ? zo : make_double2(zo.x + beta * po.x, zo.y + beta * po.y);
+        const double2 zo = wide(zn[r][kk]), po = wide(pn_old[r][kk]);
+        pn[kk] = fresh ? zo : wide(narrow<V2>(zo.x + beta * po.x, zo.y + beta * po.y));
       }
-      double2 pi = zi[r];
-      if (k != 0) pi = make_double2(zi[r].x + beta * pi_old[r].x, zi[r].y + beta * pi_old[r].y);
-      pnew[i] = pi;
-      const double2 qi = apply_row(a, i, pi, pn);
-      a.q[i] = qi;
-      acc[0] += pi.x * qi.x + pi.y * qi.y;
+      const double2 zw = wide(zi[r]);
+      V2 ps = zi[r];
+      if (!fresh) {
+        const double2 po = wide(pi_old[r]);
+        ps = narrow<V2>(zw.x + beta * po.x, zw.y + beta * po.y);
+      }
+      pnew[i] = ps;
+      const double2 pi = wide(ps);
+      const double2 qi = apply_row(a.w, a.dm, a.n, i, pi, pn);
+      const V2 qs = narrow<V2>(qi.x, qi.y);
+      a.q[i] = qs;
+      const double2 qw = wide(qs);
+      acc[0] += pi.x * qw.x + pi.y * qw.y;
     }
   }
   block_sum<1>(acc);
   if (threadIdx.x == 0) a.part[t] = acc[0];
 }
 
-__global__ void __launch_bounds__(kCoupledBlock) k_cc_update(CA a, int k) {
+template <typename T>
+__global__ void __launch_bounds__(kCoupledBlock) k_cc_update(CA<T> a, int k) {
+  using V2 = typename CA<T>::V2;
   if (*a.flag) return;
   const double pq = sum_tiles(a.part, a.n_tiles);
   if (!(pq > 0.0) || !isfinite(pq)) {
@@ -227,33 +301,39 @@ __global__ void __launch_bounds__(kCoupledBlock) k_cc_update(CA a, int k) {
     return;
   }
   const double alpha = a.scal[k & 1] / pq;
-  const double2* __restrict__ p = (k & 1) ? a.p1 : a.p0;
+  const V2* __restrict__ p = (k & 1) ? a.p1 : a.p0;
   int t, r0, r1;
   tile_rows(a, t, r0, r1);
   double acc[1] = {0.0};
   for (int i = r0 + (int)threadIdx.x; i < r1; i += blockDim.x) {
-    const double2 pi = p[i], qi = a.q[i];
-    double2 xi = a.x[i], ri = a.r[i];
+    const double2 pi = wide(p[i]), qi = wide(a.q[i]);
+    double2 xi = a.x[i];
+    const double2 rw = wide(a.r[i]);
     xi.x += alpha * pi.x;
     xi.y += alpha * pi.y;
-    ri.x -= alpha * qi.x;
-    ri.y -= alpha * qi.y;
+    const V2 rs = narrow<V2>(rw.x - alpha * qi.x, rw.y - alpha * qi.y);
+    const double2 ri = wide(rs);
     const double i11 = a.inv[i], i12 = a.inv[(size_t)a.n + i], i22 = a.inv[2 * (size_t)a.n + i];
-    const double2 zi = make_double2(i11 * ri.x + i12 * ri.y, i12 * ri.x + i22 * ri.y);
+    const V2 zs = narrow<V2>(i11 * ri.x + i12 * ri.y, i12 * ri.x + i22 * ri.y);
+    const double2 zi = wide(zs);
     a.x[i] = xi;
-    a.r[i] = ri;
-    a.z[i] = zi;
+    a.r[i] = rs;
+    a.z[i] = zs;
     acc[0] += ri.x * zi.x + ri.y * zi.y;
   }
   block_sum<1>(acc);
   if (threadIdx.x == 0) a.part[(size_t)(1 + ((k + 1) & 1)) * a.n_tiles + t] = acc[0];
 }
 
-// Partials of ||b - C x||^2 (plain float64) into part[0 .. n_tiles).
-__global__ void __launch_bounds__(kCoupledBlock) k_cc_resid(CA a) {
+// Partials of ||b - C x||^2 (float64 matrix and x) into part[0 .. n_tiles).
+// With replace set, r becomes the true residual (rounded to T), z its
+// preconditioned value, and their r.z partials go to the fourth slot.
+template <typename T>
+__global__ void __launch_bounds__(kCoupledBlock) k_cc_resid(CA<T> a, int replace) {
+  using V2 = typename CA<T>::V2;
   int t, r0, r1;
   tile_rows(a, t, r0, r1);
-  double acc[1] = {0.0};
+  double acc[2] = {0.0, 0.0};
   for (int i = r0 + (int)threadIdx.x; i < r1; i += blockDim.x) {
     double2 xn[3];
 #pragma unroll
@@ -261,13 +341,27 @@ __global__ void __launch_bounds__(kCoupledBlock) k_cc_resid(CA a) {
       const int o = a.nb[(size_t)kk * a.n + i];
       xn[kk] = o >= 0 ? a.x[o] : make_double2(0.0, 0.0);
     }
-    const double2 cx = apply_row(a, i, a.x[i], xn);
+    const double2 cx = apply_row(a.w64, a.dm64, a.n, i, a.x[i], xn);
     const double2 bi = a.b[i];
     const double tx = bi.x - cx.x, ty = bi.y - cx.y;
     acc[0] += tx * tx + ty * ty;
+    if (replace) {
+      const V2 rs = narrow<V2>(tx, ty);
+      const double2 ri = wide(rs);
+      const double i11 = a.inv[i], i12 = a.inv[(size_t)a.n + i],
+                   i22 = a.inv[2 * (size_t)a.n + i];
+      const V2 zs = narrow<V2>(i11 * ri.x + i12 * ri.y, i12 * ri.x + i22 * ri.y);
+      const double2 zi = wide(zs);
+      a.r[i] = rs;
+      a.z[i] = zs;
+      acc[1] += ri.x * zi.x + ri.y * zi.y;
+    }
   }
-  block_sum<1>(acc);
-  if (threadIdx.x == 0) a.part[t] = acc[0];
+  block_sum<2>(acc);
+  if (threadIdx.x == 0) {
+    a.part[t] = acc[0];
+    if (replace) a.part[3 * (size_t)a.n_tiles + t] = acc[1];
+  }
 }
 
 __global__ void k_cc_scatter(int n, const int* __restrict__ perm, const double2* __restrict__ x,
@@ -291,7 +385,8 @@ __global__ void k_cc_scatter(int n, const int* __restrict__ perm, const double2*
 
 // Copies the n_tiles partials at part and the flag to the host; returns
 // their fixed-order sum in *sum and the flag in *flag.
-int fetch_sum(const CA& a, double* h_part, hipStream_t s, double* sum, int32_t* flag) {
+template <typename T>
+int fetch_sum(const CA<T>& a, double* h_part, hipStream_t s, double* sum, int32_t* flag) {
   CC_HIP(hipMemcpyAsync(h_part, a.part, sizeof(double) * a.n_tiles, hipMemcpyDeviceToHost, s));
   CC_HIP(hipMemcpyAsync(h_part + a.n_tiles, a.flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   CC_HIP(hipStreamSynchronize(s));
@@ -302,32 +397,14 @@ int fetch_sum(const CA& a, double* h_part, hipStream_t s, double* sum, int32_t* 
   return PM_OK;
 }
 
-}  // namespace
-
-int coupled_pcg(const CoupledIn& in, CoupledWork& w, double tol, int max_it, int check_every,
-                pm_info* info, hipStream_t s) {
-  CA a;
-  a.n = in.n;
-  a.tile_rows = w.tile_rows;
-  a.n_tiles = w.n_tiles;
-  a.nb = in.nb;
-  a.w = w.w;
-  a.dm = w.dm;
-  a.inv = w.inv;
-  a.b = w.b;
-  a.x = w.x;
-  a.r = w.r;
-  a.z = w.z;
-  a.q = w.q;
-  a.p0 = w.p[0];
-  a.p1 = w.p[1];
-  a.part = w.part;
-  a.scal = w.scal;
-  a.flag = w.flag;
+template <typename T>
+int run(const CoupledIn& in, CoupledWork& w, CA<T>& a, double tol, int max_it, int check_every,
+        pm_info* info, hipStream_t s) {
+  const bool mixed = sizeof(T) == sizeof(float);
   const int grid = a.n_tiles;
   CC_HIP(hipMemsetAsync(a.flag, 0, sizeof(int32_t), s));
-  k_cc_setup<<<grid, kCoupledBlock, 0, s>>>(a, in.perm, in.pos, in.diagpos, in.val_x, in.val_y,
-                                           in.mA, in.b_x, in.b_y);
+  k_cc_setup<T><<<grid, kCoupledBlock, 0, s>>>(a, in.perm, in.pos, in.diagpos, in.val_x,
+                                              in.val_y, in.mA, in.b_x, in.b_y);
   CC_HIP(hipGetLastError());
   double bb = 0.0;
   int32_t flag = 0;
@@ -351,11 +428,11 @@ int coupled_pcg(const CoupledIn& in, CoupledWork& w, double tol, int max_it, int
     while (k < max_it) {
       const int steps = std::min(check_every - k % check_every, max_it - k);
       for (int j = 0; j < steps; ++j, ++k) {
-        k_cc_spmv<<<grid, kCoupledBlock, 0, s>>>(a, k);
-        k_cc_update<<<grid, kCoupledBlock, 0, s>>>(a, k);
+        k_cc_spmv<T><<<grid, kCoupledBlock, 0, s>>>(a, k, mixed && j == 0 && k > 0);
+        k_cc_update<T><<<grid, kCoupledBlock, 0, s>>>(a, k);
       }
       CC_HIP(hipGetLastError());
-      k_cc_resid<<<grid, kCoupledBlock, 0, s>>>(a);
+      k_cc_resid<T><<<grid, kCoupledBlock, 0, s>>>(a, mixed ? 1 : 0);
       double r2 = 0.0;
       if (int r = fetch_sum(a, w.h_part, s, &r2, &flag)) return r;
       rel = std::sqrt(r2) / res.bnorm;
@@ -377,6 +454,56 @@ int coupled_pcg(const CoupledIn& in, CoupledWork& w, double tol, int max_it, int
   res.status = status;
   if (info) *info = res;
   return status;
+}
+
+}  // namespace
+
+int coupled_pcg(const CoupledIn& in, CoupledWork& w, int precision, double tol, int max_it,
+                int check_every, pm_info* info, hipStream_t s) {
+  if (precision == PM_MIXED) {
+    CA<float> a;
+    a.n = in.n;
+    a.tile_rows = w.tile_rows;
+    a.n_tiles = w.n_tiles;
+    a.nb = in.nb;
+    a.w = w.w32;
+    a.dm = w.dm32;
+    a.inv = w.inv32;
+    a.w64 = w.w64;
+    a.dm64 = w.dm64;
+    a.b = w.b;
+    a.x = w.x;
+    a.r = w.r32;
+    a.z = w.z32;
+    a.q = w.q32;
+    a.p0 = w.p32[0];
+    a.p1 = w.p32[1];
+    a.part = w.part;
+    a.scal = w.scal;
+    a.flag = w.flag;
+    return run(in, w, a, tol, max_it, check_every, info, s);
+  }
+  CA<double> a;
+  a.n = in.n;
+  a.tile_rows = w.tile_rows;
+  a.n_tiles = w.n_tiles;
+  a.nb = in.nb;
+  a.w = w.w64;
+  a.dm = w.dm64;
+  a.inv = w.inv64;
+  a.w64 = w.w64;
+  a.dm64 = w.dm64;
+  a.b = w.b;
+  a.x = w.x;
+  a.r = w.r;
+  a.z = w.z;
+  a.q = w.q;
+  a.p0 = w.p[0];
+  a.p1 = w.p[1];
+  a.part = w.part;
+  a.scal = w.scal;
+  a.flag = w.flag;
+  return run(in, w, a, tol, max_it, check_every, info, s);
 }
 
 }  // namespace pm

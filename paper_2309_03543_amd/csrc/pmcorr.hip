@@ -588,7 +588,6 @@ struct pm_mesh {
   double *mA = nullptr, *ppart = nullptr, *h_part = nullptr;           // [n], [blocks][4], pinned
   // coupled CP1 conjugate gradients: workspace, created by the first call
   CoupledWork cw;
-  bool cw_ready = false;
   // the solver workspace (a set with one system)
   SolveSet set;
   std::vector<void*> allocs;
@@ -1024,37 +1023,43 @@ int ensure_pair(pm_mesh* m) {
   return PM_OK;
 }
 
-// The coupled-CG workspace, on first use.
-int ensure_coupled(pm_mesh* m) {
-  if (m->cw_ready) return PM_OK;
+// The coupled-CG workspace of one precision (and the shared part), on first
+// use.
+int ensure_coupled(pm_mesh* m, int precision) {
   CoupledWork& w = m->cw;
   const size_t n = m->n;
-  w.tile_rows = kCoupledTile;
-  w.n_tiles = coupled_tiles(m->n);
-  double2* v2[7];
   int r = PM_OK;
-  if ((!m->mA && (r = dalloc(m, &m->mA, n))) || (r = dalloc(m, &w.w, 3 * n)) ||
-      (r = dalloc(m, &w.dm, 3 * n)) || (r = dalloc(m, &w.inv, 3 * n)) ||
-      (r = dalloc(m, &w.part, 3 * (size_t)w.n_tiles)) || (r = dalloc(m, &w.scal, 2)) ||
-      (r = dalloc(m, &w.flag, 1)))
-    return r;
-  for (auto& p : v2)
-    if ((r = dalloc(m, &p, n))) return r;
-  w.b = v2[0];
-  w.x = v2[1];
-  w.r = v2[2];
-  w.z = v2[3];
-  w.q = v2[4];
-  w.p[0] = v2[5];
-  w.p[1] = v2[6];
-  hipError_t e = hipHostMalloc((void**)&w.h_part, sizeof(double) * (w.n_tiles + 1),
-                               hipHostMallocDefault);
-  if (e != hipSuccess) {
-    w.h_part = nullptr;
-    set_error(PM_HIP_ERROR, std::string("hipHostMalloc: ") + hipGetErrorString(e));
-    return PM_HIP_ERROR;
+  if (!w.ready) {
+    w.tile_rows = kCoupledTile;
+    w.n_tiles = coupled_tiles(m->n);
+    if ((!m->mA && (r = dalloc(m, &m->mA, n))) || (r = dalloc(m, &w.w64, 3 * n)) ||
+        (r = dalloc(m, &w.dm64, 3 * n)) || (r = dalloc(m, &w.b, n)) ||
+        (r = dalloc(m, &w.x, n)) || (r = dalloc(m, &w.part, 4 * (size_t)w.n_tiles)) ||
+        (r = dalloc(m, &w.scal, 2)) || (r = dalloc(m, &w.flag, 1)))
+      return r;
+    hipError_t e = hipHostMalloc((void**)&w.h_part, sizeof(double) * (w.n_tiles + 1),
+                                 hipHostMallocDefault);
+    if (e != hipSuccess) {
+      w.h_part = nullptr;
+      set_error(PM_HIP_ERROR, std::string("hipHostMalloc: ") + hipGetErrorString(e));
+      return PM_HIP_ERROR;
+    }
+    w.ready = true;
   }
-  m->cw_ready = true;
+  if (precision == PM_FP64 && !w.ready64) {
+    if ((r = dalloc(m, &w.inv64, 3 * n)) || (r = dalloc(m, &w.r, n)) || (r = dalloc(m, &w.z, n)) ||
+        (r = dalloc(m, &w.q, n)) || (r = dalloc(m, &w.p[0], n)) || (r = dalloc(m, &w.p[1], n)))
+      return r;
+    w.ready64 = true;
+  }
+  if (precision == PM_MIXED && !w.ready32) {
+    if ((r = dalloc(m, &w.w32, 3 * n)) || (r = dalloc(m, &w.dm32, 3 * n)) ||
+        (r = dalloc(m, &w.inv32, 3 * n)) || (r = dalloc(m, &w.r32, n)) ||
+        (r = dalloc(m, &w.z32, n)) || (r = dalloc(m, &w.q32, n)) ||
+        (r = dalloc(m, &w.p32[0], n)) || (r = dalloc(m, &w.p32[1], n)))
+      return r;
+    w.ready32 = true;
+  }
   return PM_OK;
 }
 
@@ -1168,11 +1173,7 @@ int cp1_solve_coupled_pcg(pm_mesh* m, const pm_cell_params* prm, double nu, doub
   pm_opts_default(&o);
   if (opts) o = *opts;
   if (int r = check_opts(o)) return r;
-  if (o.precision != PM_FP64) {
-    set_error(PM_INVALID_ARG, "cp1_solve_coupled_pcg: float64 only");
-    return PM_INVALID_ARG;
-  }
-  if (int r = ensure_coupled(m)) return r;
+  if (int r = ensure_coupled(m, o.precision)) return r;
   PM_HIP(hipMemsetAsync(m->asm_err, 0, sizeof(int32_t), s));
   k_cp1_mass<<<blocks_for(m->n, 256), 256, 0, s>>>(m->n, m->perm, prm->eps, prm->logk, prm->chi,
                                                    prm->g11, prm->g12, prm->g22, nu, dt, m->area,
@@ -1197,7 +1198,7 @@ int cp1_solve_coupled_pcg(pm_mesh* m, const pm_cell_params* prm, double nu, doub
   in.b_y = b_y;
   in.u = u;
   in.v = v;
-  return coupled_pcg(in, m->cw, o.tol, o.max_it, o.replace_every, info, s);
+  return coupled_pcg(in, m->cw, o.precision, o.tol, o.max_it, o.replace_every, info, s);
 }
 
 int flux_average(pm_mesh* m, const double* u, const double* v, const double* g_u,

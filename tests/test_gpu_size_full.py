@@ -199,9 +199,11 @@ def test_aniso_channel_4M_coupled_cp1():
     assert rx <= 1e-10 and ry <= 1e-10
 
 
-def test_aniso_channel_4M_coupled_cp1_pcg():
-    """Block-Jacobi CG on the coupled CP1 system of the 4M anisotropic channel:
-    true relative residual <= 1e-10 under the oracle's coupled matrix."""
+@pytest.mark.parametrize("precision", [0, 1])
+def test_aniso_channel_4M_coupled_cp1_pcg(precision):
+    """Block-Jacobi CG on the coupled CP1 system of the 4M anisotropic channel,
+    float64 and mixed: true relative residual <= 1e-10 under the oracle's
+    coupled matrix."""
     from oracle import cp1coupled as occ
 
     c = dict(channel_case(552, 3, True), key=(552, 3, True))
@@ -211,7 +213,7 @@ def test_aniso_channel_4M_coupled_cp1_pcg():
     bx, by = w["rhs"]["cp1x"], w["rhs"]["cp1y"]
     u, v, info = B().cp1_solve_coupled_pcg(c["mesh"], c["prm"], w["nu"], w["dt"], vx, vy,
                                            torch.tensor(bx, device=c["dev"]),
-                                           torch.tensor(by, device=c["dev"]))
+                                           torch.tensor(by, device=c["dev"]), precision=precision)
     perm = c["perm"]
     Ax = oracle_system(552, 3, True, "cp1x")["A"]
     Ay = oracle_system(552, 3, True, "cp1y")["A"]
@@ -220,7 +222,7 @@ def test_aniso_channel_4M_coupled_cp1_pcg():
     b = np.concatenate([bx[perm], by[perm]])
     x = np.concatenate([u.cpu().numpy()[perm], v.cpu().numpy()[perm]])
     res = np.linalg.norm(b - C @ x) / np.linalg.norm(b)
-    log(f"aniso 4M coupled CP1 CG: {info['iters']} iterations, residual {res:.2e} "
+    log(f"aniso 4M coupled CP1 CG precision {precision}: {info['iters']} iterations, residual {res:.2e} "
         f"(reported {info['rel_res_true']:.2e})")
     assert info["status"] == 0 and res <= 1e-10
 
