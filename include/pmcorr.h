@@ -189,6 +189,15 @@ int pm_mesh_create(int32_t n_nodes, const double* xy, int32_t n_cells, const int
                    const int8_t* side_tag, pm_mesh** out);
 void pm_mesh_destroy(pm_mesh* mesh);
 int pm_mesh_get_stats(const pm_mesh* mesh, pm_mesh_stats* stats);
+/*
+ * Sets the width of the column offsets the solver streams for this mesh's
+ * single-system solves: 32 always works; 16, the default whenever it fits,
+ * needs an RCM bandwidth of at most 32767.  Wider offsets cost 6 bytes more
+ * per row and iteration; the call lets the 32-bit path run on meshes of any
+ * size (test it, or compare).  It resets the mesh's solver workspace;
+ * pm_mesh_get_stats reports the width in use.  Errors: PM_INVALID_ARG.
+ */
+int pm_mesh_set_index_bits(pm_mesh* mesh, int32_t bits);
 /* Host copies of the ordering and the CSR pattern (sizes n_cells, n_cells+1, nnz). */
 int pm_mesh_export(const pm_mesh* mesh, int32_t* perm, int32_t* row_ptr, int32_t* col);
 

@@ -81,6 +81,7 @@ def lib():
             "pm_mesh_destroy": (None, [P]),
             "pm_mesh_get_stats": (C.c_int, [P, P]),
             "pm_mesh_export": (C.c_int, [P, P, P, P]),
+            "pm_mesh_set_index_bits": (C.c_int, [P, I32]),
             "assemble_corrector": (C.c_int, [P, I32, P, D, D, P, P, P, P, P, P]),
             "pcg_solve": (C.c_int, [P, P, P, P, P, P, P]),
             "pm_batch_create": (C.c_int, [I32, P, C.POINTER(P)]),
@@ -183,6 +184,13 @@ class Mesh:
         col = np.empty(self.nnz, np.int32)
         _check(lib().pm_mesh_export(self.handle, _ptr(perm), _ptr(row_ptr), _ptr(col)))
         return perm, row_ptr, col
+
+    def set_index_bits(self, bits: int):
+        """Width of the solver's column offsets (16 or 32)."""
+        _check(lib().pm_mesh_set_index_bits(self.handle, int(bits)))
+        st = pm_mesh_stats()
+        _check(lib().pm_mesh_get_stats(self.handle, C.addressof(st)))
+        self.stats = st.as_dict()
 
     def close(self):
         if self.handle:
@@ -449,7 +457,7 @@ def pm_last_launch(mesh: Mesh) -> dict:
 
 EXPORTED = [
     "pm_opts_default", "pm_status_string", "pm_last_error", "pm_structure_host", "pm_mesh_create",
-    "pm_mesh_destroy", "pm_mesh_get_stats", "pm_mesh_export", "assemble_corrector", "pcg_solve",
+    "pm_mesh_destroy", "pm_mesh_get_stats", "pm_mesh_export", "pm_mesh_set_index_bits", "assemble_corrector", "pcg_solve",
     "pm_batch_create", "pm_batch_destroy", "pm_batch_offsets", "pcg_solve_batched", "pcg_adjoint",
     "pm_time_kernel", "pm_last_launch", "cp2_cross_rhs", "pm_time_cross",
     "cp2_solve_two_step", "cp1_solve_coupled", "cp1_solve_coupled_pcg", "flux_average",

@@ -833,6 +833,18 @@ int pm_mesh_get_stats(const pm_mesh* m, pm_mesh_stats* st) {
   return PM_OK;
 }
 
+int pm_mesh_set_index_bits(pm_mesh* m, int32_t bits) {
+  if (!m || (bits != 16 && bits != 32) || (bits == 16 && m->hs.stats.bandwidth > 32767)) {
+    set_error(PM_INVALID_ARG, "pm_mesh_set_index_bits: 16 or 32 bits (16 needs bandwidth <= 32767)");
+    return PM_INVALID_ARG;
+  }
+  set_free(m->set);
+  if (int r = set_init(m->set, std::vector<int>{m->n}, m->nnz, bits, m->perm, m->row_ptr, m->col))
+    return r;
+  m->hs.stats.index_bits = bits;
+  return PM_OK;
+}
+
 int pm_mesh_export(const pm_mesh* m, int32_t* perm, int32_t* row_ptr, int32_t* col) {
   if (!m) {
     set_error(PM_INVALID_ARG, "null mesh");

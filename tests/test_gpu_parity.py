@@ -273,3 +273,38 @@ def test_unreachable_tolerance_stagnates_like_the_oracle():
     c, A, b, xg, info, xo, io = solve_both("tiny", "cp2", 0, tol=1e-19, stag_checks=10)
     assert info["status"] == B().PM_STAGNATED and io["status"] == opcg.STAGNATED
     assert opcg.rel_residual(A, b, xg) < 1e-12
+
+
+def test_wide_column_offsets_match_narrow_bitwise():
+    """32-bit column indices (the path of meshes whose RCM bandwidth exceeds
+    32767) give bitwise the same solutions as the 16-bit offsets, for every
+    schedule, both precisions and both preconditioners, at fixed launch
+    shapes; 16 bits are restored afterwards."""
+    c = case("chan")
+    w = c["w"]
+    mesh = c["mesh"]
+    val = B().assemble_corrector(mesh, B().PM_CP2, c["prm"], w["nu"], w["dt"])["val64"]
+    b = torch.tensor(w["rhs"]["cp2"], device=c["dev"])
+    shapes = [dict(tile_rows=1024, block=256, iter_shape=1), dict(tile_rows=2048, block=256, iter_shape=2),
+              dict(tile_rows=2048, block=512, iter_shape=3), dict(tile_rows=1024, block=256, iter_shape=-1)]
+    runs = []
+    try:
+        for bits in (16, 32):
+            mesh.set_index_bits(bits)
+            assert mesh.stats["index_bits"] == bits
+            out = []
+            for prec in (0, 1):
+                for sh in shapes:
+                    x, info = B().pcg_solve(mesh, val, b, precision=prec, **sh)
+                    out.append((x.cpu().numpy(), info["iters"], info["status"]))
+                x, info = B().pcg_solve(mesh, val, b, precision=prec, precond=1, cheb_degree=4,
+                                        tile_rows=2048, block=256)
+                out.append((x.cpu().numpy(), info["iters"], info["status"]))
+            runs.append(out)
+    finally:
+        mesh.set_index_bits(16)
+    for (x16, it16, st16), (x32, it32, st32) in zip(*runs):
+        assert st16 == 0 and st32 == 0 and it16 == it32
+        assert np.array_equal(x16, x32)
+    with pytest.raises(B().PMError):
+        mesh.set_index_bits(8)
