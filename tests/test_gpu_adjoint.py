@@ -51,7 +51,7 @@ def forward(c, kind, params_np, g=None):
     return prm, gd, out, rhs, x
 
 
-@pytest.mark.parametrize("name,kind", [("iso", 2), ("aniso", 2), ("iso", 0)])
+@pytest.mark.parametrize("name,kind", [("iso", 2), ("aniso", 2), ("iso", 0), ("aniso", 1)])
 def test_adjoint_matches_cpu_adjoint_and_finite_differences(name, kind):
     c = case(name)
     w = c["w"]
