@@ -34,6 +34,7 @@ def build(verbose: bool = False) -> str:
         ("solver.hip", COMMON + DEVICE),
         ("batched.hip", COMMON + DEVICE),
         ("coupled.hip", COMMON + DEVICE),
+        ("step.hip", COMMON + DEVICE),
     ]
     procs = []
     for src, flags in jobs:
