@@ -10,11 +10,16 @@
  * This library builds their sparsity once per mesh, assembles their values
  * from per-cell porosity and permeability on the GPU, and solves them with
  * Jacobi- or Chebyshev-polynomial-preconditioned conjugate gradients on the
- * GPU (single systems or batches of systems of uneven size), with a
- * hand-written adjoint for gradients with respect to the cell parameters and
- * the co-normal cross terms that form the right-hand side of the second CP2
- * solve, the coupled anisotropic CP1, and the averaged side fluxes and RT0
- * velocity around the CP2.
+ * GPU (single systems or batches of systems of uneven size).  Around the
+ * solves it provides
+ *   - a hand-written adjoint for gradients with respect to the cell
+ *     parameters;
+ *   - the co-normal cross terms that form the right-hand side of the second
+ *     CP2 solve, and that two-solve sequence;
+ *   - the coupled anisotropic CP1 (the paper's loop, or conjugate gradients
+ *     on both components);
+ *   - the averaged side fluxes that feed the CP2 and the RT0 velocity after
+ *     it.
  *
  * Conventions shared by every entry point
  *   - Triangles are given counter-clockwise; side j of triangle e is the side
