@@ -275,22 +275,34 @@ def main():
     if tmesh is not None:
         launch = B.pm_last_launch(tmesh)
         fused = launch["iter_shape"] > 0
-        it_name = "k_iter" if fused else "k_update+k_spmv"
-        for name, which, reps in (("k_spmv", 0, 200), (it_name, 1, 200), ("k_resid", 2, 20)):
+        resident = launch["iter_shape"] == 4
+        it_name = "k_chunk" if resident else "k_iter" if fused else "k_update+k_spmv"
+        # the resident kernel runs a chunk's m - 1 = 49 iterations per launch
+        per_launch = 49 if resident else 1
+        for name, which, reps in (("k_spmv", 0, 200), (it_name, 1, 8 if resident else 200),
+                                  ("k_resid", 2, 20)):
             ms, by = B.pm_time_kernel(tmesh, which, reps)
-            kern[name] = {"ms": ms, "bytes": by, "GBs": by / ms / 1e6,
+            k = per_launch if name == it_name else 1
+            kern[name] = {"ms": ms * k, "bytes": by * k, "GBs": by / ms / 1e6,
                           "frac_hbm": by / ms / 1e6 / HBM_PEAK_GBS}
+            if k > 1:
+                kern[name]["iterations_per_launch"] = k
         kern["launch"] = launch
         it_last = inf64[-1][-1]["iters"]
         # fused: one k_iter launch per iteration (k_spmv opens each chunk of 50);
-        # split: k_spmv is the larger of the iteration's two kernels
-        dom = "k_iter" if fused else "k_spmv"
+        # resident: one k_chunk launch per chunk; split: k_spmv is the larger of
+        # the iteration's two kernels
+        dom = it_name if fused else "k_spmv"
         achieved = kern[dom]["GBs"]
         roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                 "traffic": measured_traffic(wname, launch, dom),
                 "ms_per_launch": kern[dom]["ms"], "bytes_per_launch": kern[dom]["bytes"],
-                "launches_per_solve": it_last}
+                "launches_per_solve": -(-it_last // 50) if resident else it_last}
+        if resident:
+            roof["note"] = ("achieved = the iterations' algorithmic bytes (what a streaming "
+                            "iteration moves) over the launch time; the resident kernel keeps "
+                            "its tiles on chip, so traffic is the bytes it actually moves")
     else:
         roof = None
 

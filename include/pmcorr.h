@@ -143,7 +143,13 @@ typedef struct {
                             fused kernel with that many rows per thread and
                             trip (0 = 1), 3 the fused kernel with the tile's
                             column window staged in LDS (PM_INVALID_ARG if it
-                            does not fit); ignored when the tuner decides */
+                            does not fit), 4 the resident chunk kernel: one
+                            launch runs the m - 1 fused iterations of a chunk
+                            with every tile's rows held on chip and a grid
+                            barrier between iterations (one system whose
+                            tiles all fit the device at once, tile_rows at
+                            most 8 x block; else PM_INVALID_ARG; pcg_solve
+                            only); ignored when the tuner decides */
 } pm_opts;
 
 typedef struct {
@@ -494,7 +500,10 @@ int pm_time_cross(pm_mesh* mesh, const pm_cell_params* params, double nu, double
  *             (update of x, z, p and the product of the new direction with
  *             its dot products in one launch), or on the split schedule the
  *             update kernel followed by the product; timed with zero step
- *             lengths, so the state does not change
+ *             lengths, so the state does not change.  On the resident
+ *             schedule n_launch launches of m - 1 iterations each are timed
+ *             (m = replace_every of the last solve) and the time per
+ *             iteration is returned
  *          2: true-residual kernel (float64 CSR, compensated)
  * Bytes per launch, n rows, vector/weight/index widths sv/sw/si:
  *   0: n (4 sw + 3 si + 3 sv)

@@ -27,6 +27,7 @@ struct SysState {
   int32_t status;           // PM_* status once stopped
   int32_t k_best;           // iteration at which res2 last fell below best_res2 / 4
   int32_t err;              // input check failure found by the preparation kernel
+  uint32_t bar;             // arrivals at the grid barrier of the resident chunk kernel
 };
 
 // A set of one or more independent systems laid out one after another.
@@ -46,7 +47,11 @@ struct SolveSet {
   int *tile_sys = nullptr, *tile_r0 = nullptr, *tile_r1 = nullptr, *sys_tile0 = nullptr;
   // columns reached by each tile's rows, [tile_lo, tile_hi], and the widest
   int *tile_lo = nullptr, *tile_hi = nullptr;
+  // rows of each tile that some other tile's window reaches: r < pub_lo or
+  // r >= pub_hi (the resident chunk kernel publishes only these per iteration)
+  int *tile_pub_lo = nullptr, *tile_pub_hi = nullptr;
   int win_max = 0;
+  int n_cu = 0;       // compute units of the device (queried once)
   int lds_limit = 0;  // bytes of LDS one block may use (queried once)
   // workspace: difference-form rows, vectors, partials, states
   void *c = nullptr, *w = nullptr, *idx = nullptr;

@@ -52,6 +52,8 @@ struct SetArgs {
   const int* sys_tile0;
   const int* tile_lo;  // first and last column any row of the tile reaches
   const int* tile_hi;
+  const int* tile_pub_lo;  // rows r < pub_lo or r >= pub_hi are in another tile's window
+  const int* tile_pub_hi;
   const int* perm;
   const int* rp;
   const int* col;
@@ -448,17 +450,21 @@ __global__ void __launch_bounds__(1024) k_spmv(SetArgs<V, W, I> a) {
 // system obtains the same sums.
 constexpr int kPartU = 4;
 
-struct PartRegs {
-  double2 v[kPartU][2];
+template <int PU>
+struct PartRegsT {
+  double2 v[PU][2];
 };
+using PartRegs = PartRegsT<kPartU>;
 
 // Branch-free: every thread loads a valid tile (its own, or the system's last
 // one) and partial_reduce() drops the copies, so no load waits on another.
+// PU tiles per thread in registers; the sum is the same for any PU.
+template <int PU>
 __device__ __forceinline__ void partial_load(const double* __restrict__ part, int t0, int t1,
-                                             PartRegs& P) {
+                                             PartRegsT<PU>& P) {
   const double2* p2 = reinterpret_cast<const double2*>(part);
 #pragma unroll
-  for (int u = 0; u < kPartU; ++u) {
+  for (int u = 0; u < PU; ++u) {
     const int tt = t0 + (int)threadIdx.x + u * (int)blockDim.x;
     const size_t tc = (size_t)(tt < t1 ? tt : t1 - 1);
     P.v[u][0] = p2[2 * tc];
@@ -466,20 +472,21 @@ __device__ __forceinline__ void partial_load(const double* __restrict__ part, in
   }
 }
 
+template <int PU>
 __device__ __forceinline__ void partial_reduce(const double* __restrict__ part, int t0, int t1,
-                                               const PartRegs& P, double (&out)[4]) {
+                                               const PartRegsT<PU>& P, double (&out)[4]) {
   __shared__ double sh[4][16];
   __shared__ double res[4];
   double v[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int u = 0; u < kPartU; ++u) {
+  for (int u = 0; u < PU; ++u) {
     const bool own = t0 + (int)threadIdx.x + u * (int)blockDim.x < t1;
     v[0] += own ? P.v[u][0].x : 0.0;
     v[1] += own ? P.v[u][0].y : 0.0;
     v[2] += own ? P.v[u][1].x : 0.0;
     v[3] += own ? P.v[u][1].y : 0.0;
   }
-  for (int tt = t0 + (int)threadIdx.x + kPartU * (int)blockDim.x; tt < t1; tt += blockDim.x)
+  for (int tt = t0 + (int)threadIdx.x + PU * (int)blockDim.x; tt < t1; tt += blockDim.x)
 #pragma unroll
     for (int k = 0; k < 4; ++k) v[k] += part[4 * (size_t)tt + k];
   wave_sum<4>(v);
@@ -810,6 +817,291 @@ __global__ void __launch_bounds__(512) k_iter_lds(SetArgs<V, W, I> a, int src, i
     S.beta = be;
     S.rho = rho;
     S.iter = k;
+  }
+}
+
+// Data that blocks of the resident chunk kernel exchange within one launch
+// (halo rows, tile partials) is written and read with device-coherent
+// accesses (relaxed atomics at agent scope: they write through and read past
+// the per-XCD L2), so the grid barrier needs no L2 write-back or invalidate.
+template <typename T>
+__device__ __forceinline__ T ld_agent(const T* p) {
+  if constexpr (sizeof(T) == 8) {
+    const unsigned long long v = __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p),
+                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __builtin_bit_cast(T, v);
+  } else {
+    const unsigned v = __hip_atomic_load(reinterpret_cast<const unsigned*>(p), __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+    return __builtin_bit_cast(T, v);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void st_agent(T* p, T x) {
+  if constexpr (sizeof(T) == 8)
+    __hip_atomic_store(reinterpret_cast<unsigned long long*>(p),
+                       __builtin_bit_cast(unsigned long long, x), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  else
+    __hip_atomic_store(reinterpret_cast<unsigned*>(p), __builtin_bit_cast(unsigned, x),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Grid barrier of the resident chunk kernel: each wave waits until its own
+// stores have completed, then the block adds one arrival to *ctr and waits
+// until all `target` arrivals of this barrier are in.  The wait is bounded
+// (about a second): a grid that is not fully resident ends with an error
+// instead of spinning for ever.
+__device__ __forceinline__ bool grid_barrier(uint32_t* ctr, uint32_t target) {
+  __shared__ int ok;
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int spins = 0;
+    constexpr int kMaxSpins = 1 << 20;
+    while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target &&
+           spins < kMaxSpins) {
+      __builtin_amdgcn_s_sleep(1);
+      ++spins;
+    }
+    ok = spins < kMaxSpins;
+  }
+  __syncthreads();
+  return ok != 0;
+}
+
+// partial_reduce over all nt tiles with device-coherent loads (same order)
+__device__ __forceinline__ void partial_reduce_agent(const double* part, int nt,
+                                                     double (&out)[4]) {
+  __shared__ double sh[4][16];
+  __shared__ double res[4];
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int tt = (int)threadIdx.x; tt < nt; tt += blockDim.x)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] += ld_agent(part + 4 * (size_t)tt + k);
+  wave_sum<4>(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) sh[k][wid] = v[k];
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    double acc = 0.0;
+    for (int w = 0; w < nw; ++w) acc += sh[threadIdx.x][w];
+    res[threadIdx.x] = acc;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 4; ++k) out[k] = res[k];
+}
+
+// block_partial with a device-coherent store of the result
+__device__ __forceinline__ void tile_partial_agent(double (&v)[4], double* part) {
+  __shared__ double sh[4][16];
+  wave_sum<4>(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) sh[k][wid] = v[k];
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    double acc = 0.0;
+    for (int w = 0; w < nw; ++w) acc += sh[threadIdx.x][w];
+    st_agent(part + threadIdx.x, acc);
+  }
+}
+
+__global__ void k_bar_reset(SysState* ss) { ss[0].bar = 0u; }
+
+// Resident chunk kernel: iterations j0 .. j1-1 of a chunk of one system in
+// one launch, with one block per tile and every block resident (the host
+// launches it only when the whole grid fits the device at once).  Each
+// iteration performs exactly the arithmetic of k_iter / k_iter_lds, bit for
+// bit, with the same fixed-order partial sums; what changes is where the
+// data lives between iterations:
+//   - the tile's matrix rows, x_acc and q~ stay in registers, its p and z in
+//     LDS (inside the staged column window), for the whole launch;
+//   - per iteration a block loads only the halo of its window (rows of other
+//     tiles) from the buffer its neighbours wrote, and stores only its own
+//     rows that fall in another tile's window, plus its tile partials;
+//   - a grid barrier replaces the kernel boundary between iterations; what
+//     crosses it is stored and loaded device-coherently.
+// The last iteration stores every row (p, z, q~ and x_acc), so the kernels
+// after the chunk find the same state as after the one-kernel-per-iteration
+// schedule.  RPT: rows per thread (RPT * blockDim >= tile rows).
+template <typename V, typename W, typename I, int RPT>
+__global__ void __launch_bounds__(512) k_chunk(SetArgs<V, W, I> a, int j0, int j1,
+                                               double scale) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const int t = xcd_block(blockIdx.x, gridDim.x);
+  SysState& S = a.ss[0];
+  if (S.done) return;
+  const int r0 = a.tile_r0[t], r1 = a.tile_r1[t];
+  const int lo = a.tile_lo[t], nwin = a.tile_hi[t] - lo + 1;
+  const int pub_lo = a.tile_pub_lo[t], pub_hi = a.tile_pub_hi[t];
+  const int nt = gridDim.x;
+  const int B = blockDim.x, tid = threadIdx.x;
+  const size_t N = (size_t)a.N;
+  V* __restrict__ lp = reinterpret_cast<V*>(lds_raw);
+  V* __restrict__ lz = lp + nwin;
+  V* __restrict__ lq = lz + nwin;  // q~ of the tile's own rows
+  // halo: window rows below the tile (nlow of them), then above it
+  const int nlow = r0 - lo, nhalo = nwin - (r1 - r0);
+  auto halo_w = [&](int h) { return h < nlow ? h : h + (r1 - r0); };
+
+  W w0[RPT], w1[RPT], w2[RPT], cc[RPT];
+  I i0[RPT], i1[RPT], i2[RPT];
+  V xa[RPT];
+#pragma unroll
+  for (int u = 0; u < RPT; ++u) {
+    const int ir = r0 + tid + u * B;
+    const int i = ir < r1 ? ir : r0;
+    w0[u] = a.w[i];
+    w1[u] = a.w[N + i];
+    w2[u] = a.w[2 * N + i];
+    i0[u] = a.idx[i];
+    i1[u] = a.idx[N + i];
+    i2[u] = a.idx[2 * N + i];
+    cc[u] = a.c[i];
+    xa[u] = a.xacc[i];
+  }
+  const bool first_block = t == 0 && tid == 0;
+  double al = 0.0, be = 0.0, rho = 0.0;
+  int k_done = -1;
+  int nbar = 0;
+  bool failed = false;
+  int src = (j0 - 1) & 1;
+  for (int j = j0; j < j1; ++j, src ^= 1) {
+    const bool first = j == j0, last = j + 1 == j1;
+    if (!first && !grid_barrier(&S.bar, (uint32_t)(++nbar) * (uint32_t)nt)) {
+      failed = true;
+      break;
+    }
+    const V* __restrict__ ps = a.p[src];
+    const V* __restrict__ zs = a.z[src];
+    const V* __restrict__ qs = a.q[src];
+    V* __restrict__ pd = a.p[src ^ 1];
+    V* __restrict__ zd = a.z[src ^ 1];
+    V* __restrict__ qd = a.q[src ^ 1];
+    // the first halo rows of this thread are in flight while the partials
+    // are reduced
+    constexpr int HR = 2;
+    V hp[HR], hz[HR], hq[HR];
+#pragma unroll
+    for (int u = 0; u < HR; ++u) {
+      const int h = tid + u * B;
+      const int i = lo + halo_w(h < nhalo ? h : (nhalo > 0 ? nhalo - 1 : 0));
+      const int ic = nhalo > 0 ? i : r0;
+      hp[u] = ld_agent(ps + ic);
+      hz[u] = ld_agent(zs + ic);
+      hq[u] = ld_agent(qs + ic);
+    }
+    double r[4];
+    partial_reduce_agent(a.part[src], nt, r);
+    const int k = S.iter_base + j;
+    const double pq = r[0], rh = r[3];
+    if (const int stop = stop_code(k, S.max_it, pq, rh)) {
+      if (first_block) {
+        S.status = stop == 100 ? PM_OK : stop;
+        S.done = 1;
+      }
+      break;
+    }
+    const double a_ = rh / pq;
+    const double rn = rh - 2.0 * a_ * r[1] + a_ * a_ * r[2];
+    const double b_ = rn / rh;
+    const double as = a_ * scale, bs = b_ * scale;
+    // staging: the new z and p of the window into LDS; own rows by the
+    // thread that owns them, which also adds alpha p (old p) to x_acc.  The
+    // first iteration reads them from the buffer, later ones from LDS.
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+      const int i = r0 + tid + u * B;
+      if (i >= r1) continue;
+      const int li = i - lo;
+      const V qold = first ? qs[i] : lq[i - r0];
+      const V pold = first ? ps[i] : lp[li];
+      const V zold = first ? zs[i] : lz[li];
+      const V zn = (V)((double)zold - as * (double)qold);
+      const V pn = (V)((double)zn + bs * (double)pold);
+      xa[u] = (V)((double)xa[u] + as * (double)pold);
+      lp[li] = pn;
+      lz[li] = zn;
+      if (last) {
+        zd[i] = zn;
+        pd[i] = pn;
+      } else if (i < pub_lo || i >= pub_hi) {
+        st_agent(zd + i, zn);
+        st_agent(pd + i, pn);
+      }
+    }
+    auto stage_halo = [&](int h, V pold, V zold, V qold) {
+      const V zn = (V)((double)zold - as * (double)qold);
+      const V pn = (V)((double)zn + bs * (double)pold);
+      const int w = halo_w(h);
+      lp[w] = pn;
+      lz[w] = zn;
+    };
+#pragma unroll
+    for (int u = 0; u < HR; ++u) {
+      const int h = tid + u * B;
+      if (h < nhalo) stage_halo(h, hp[u], hz[u], hq[u]);
+    }
+    for (int h = tid + HR * B; h < nhalo; h += B) {
+      const int i = lo + halo_w(h);
+      stage_halo(h, ld_agent(ps + i), ld_agent(zs + i), ld_agent(qs + i));
+    }
+    __syncthreads();
+    // product of the new direction for own rows, with the tile partials
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+      const int i = r0 + tid + u * B;
+      if (i >= r1) continue;
+      const int li = i - lo;
+      const double pi = (double)lp[li], zi = (double)lz[li], ci = (double)cc[u];
+      double y = ci * pi;
+      y += (double)w0[u] * (pi - (double)lp[col_of<I>(i, i0[u]) - lo]);
+      y += (double)w1[u] * (pi - (double)lp[col_of<I>(i, i1[u]) - lo]);
+      y += (double)w2[u] * (pi - (double)lp[col_of<I>(i, i2[u]) - lo]);
+      const double d = ((ci + (double)w0[u]) + (double)w1[u]) + (double)w2[u];
+      const V qn = (V)(y / d);
+      lq[i - r0] = qn;
+      if (last) qd[i] = qn;
+      else if (i < pub_lo || i >= pub_hi) st_agent(qd + i, qn);
+      const double qq = (double)qn;
+      const double dq = d * qq;
+      acc[0] += pi * dq;
+      acc[1] += zi * dq;
+      acc[2] += qq * dq;
+      acc[3] += d * zi * zi;
+    }
+    tile_partial_agent(acc, a.part[src ^ 1] + 4 * (size_t)t);
+    al = a_;
+    be = b_;
+    rho = rh;
+    k_done = k;
+  }
+  // x_acc of the completed iterations (also after a stop, which leaves the
+  // state of the last completed iteration, as the per-iteration kernels do)
+#pragma unroll
+  for (int u = 0; u < RPT; ++u) {
+    const int i = r0 + tid + u * B;
+    if (i < r1) a.xacc[i] = xa[u];
+  }
+  if (first_block) {
+    if (k_done >= 0) {
+      S.alpha = al;
+      S.beta = be;
+      S.rho = rho;
+      S.iter = k_done;
+    }
+  }
+  if (failed && tid == 0) {  // any block that gave up marks the solve failed
+    S.status = PM_HIP_ERROR;
+    S.done = 1;
   }
 }
 
@@ -1271,6 +1563,23 @@ int build_tiles(SolveSet& S, int tile_rows) {
   PS_HIP(hipMemcpy(hi.data(), S.tile_hi, 4 * (size_t)nt, hipMemcpyDeviceToHost));
   S.win_max = 0;
   for (int k = 0; k < nt; ++k) S.win_max = std::max(S.win_max, hi[k] - lo[k] + 1);
+  // published rows: those at or below the highest column of an earlier tile
+  // of the system, and those at or above the lowest column of a later one
+  std::vector<int> plo(nt), phi(nt);
+  for (int sy = 0; sy < S.n_sys; ++sy) {
+    int run = INT_MIN;
+    for (int k = st0[sy]; k < st0[sy + 1]; ++k) {
+      plo[k] = run == INT_MIN ? INT_MIN : run + 1;
+      run = std::max(run, hi[k]);
+    }
+    run = INT_MAX;
+    for (int k = st0[sy + 1] - 1; k >= st0[sy]; --k) {
+      phi[k] = run;
+      run = std::min(run, lo[k]);
+    }
+  }
+  PS_HIP(hipMemcpy(S.tile_pub_lo, plo.data(), 4 * (size_t)nt, hipMemcpyHostToDevice));
+  PS_HIP(hipMemcpy(S.tile_pub_hi, phi.data(), 4 * (size_t)nt, hipMemcpyHostToDevice));
   S.tile_rows = tile_rows;
   S.n_tiles = nt;
   return PM_OK;
@@ -1287,6 +1596,8 @@ SetArgs<V, W, I> make_args(SolveSet& S, const double* val, const double* b, doub
   a.sys_tile0 = S.sys_tile0;
   a.tile_lo = S.tile_lo;
   a.tile_hi = S.tile_hi;
+  a.tile_pub_lo = S.tile_pub_lo;
+  a.tile_pub_hi = S.tile_pub_hi;
   a.perm = S.perm;
   a.rp = S.rp;
   a.col = S.col;
@@ -1347,6 +1658,8 @@ Cheb make_cheb(int degree) {
 struct Launch {
   int tile, block, rows;
 };
+// Launch.rows of the resident chunk kernel (k_chunk)
+constexpr int kResident = 4;
 
 template <typename V, typename W, typename I>
 struct Ops {
@@ -1400,12 +1713,58 @@ struct Ops {
     }
     return true;
   }
+  // Resident chunk kernel (Launch.rows == kResident): rows per thread, 4 or 8.
+  static int resident_rpt(int tile, int block) {
+    return tile <= 4 * block ? 4 : tile <= 8 * block ? 8 : 0;
+  }
+  static const void* resident_fn(int rpt) {
+    return rpt == 4 ? (const void*)k_chunk<V, W, I, 4> : (const void*)k_chunk<V, W, I, 8>;
+  }
+  // whether every tile of the current set can be resident at once (one system,
+  // its window in LDS, the whole grid on the device together)
+  static size_t resident_lds_bytes(const SolveSet& S) {
+    return sizeof(V) * (2 * (size_t)S.win_max + (size_t)S.tile_rows);
+  }
+  static bool resident_fits(const SolveSet& S, const Launch& L) {
+    const int rpt = resident_rpt(L.tile, L.block);
+    if (S.n_sys != 1 || rpt == 0 || S.n_cu <= 0) return false;
+    const size_t need = resident_lds_bytes(S);
+    if (need > (size_t)S.lds_limit) return false;
+    const void* f = resident_fn(rpt);
+    if (need > 65536 &&
+        hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)need) !=
+            hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, L.block, need) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    return (long)per_cu * S.n_cu >= (long)S.n_tiles;
+  }
+  // iterations j0 .. j1-1 of a chunk in one resident launch (buffer (j0-1)&1 in)
+  static void resident(SolveSet& S, const A& a, int j0, int j1, const Launch& L, hipStream_t s,
+                       double scale) {
+    k_bar_reset<<<1, 1, 0, s>>>(S.ss);
+    const size_t lds = resident_lds_bytes(S);
+    if (resident_rpt(L.tile, L.block) == 4)
+      k_chunk<V, W, I, 4><<<S.n_tiles, L.block, lds, s>>>(a, j0, j1, scale);
+    else
+      k_chunk<V, W, I, 8><<<S.n_tiles, L.block, lds, s>>>(a, j0, j1, scale);
+  }
   static void chunk(SolveSet& S, const A& a, int m, const Launch& L, hipStream_t s) {
     spmv(S, a, L, s);
     int src = 0;
-    for (int j = 1; j < m; ++j) {
-      iter(S, a, src, j, L, s, 1.0);
-      if (L.rows != 0) src ^= 1;
+    if (L.rows == kResident) {
+      if (m > 1) resident(S, a, 1, m, L, s, 1.0);
+      src = (m - 1) & 1;
+    } else {
+      for (int j = 1; j < m; ++j) {
+        iter(S, a, src, j, L, s, 1.0);
+        if (L.rows != 0) src ^= 1;
+      }
     }
     k_update_flush<V, W, I><<<S.n_tiles, L.block, 0, s>>>(a, src, m);
     resid(S, a, 1, L, s);
@@ -1458,6 +1817,7 @@ constexpr Launch kCandidates[] = {
     {1024, 256, 1}, {2048, 256, 1}, {2048, 512, 1}, {4096, 512, 1}, {2048, 256, 2},
     {4096, 512, 2}, {8192, 512, 2}, {2048, 256, 0}, {4096, 256, 0}, {4096, 512, 0},
     {1024, 256, 3}, {2048, 256, 3}, {2048, 512, 3}, {4096, 512, 3}, {8192, 512, 3},
+    {2048, 256, 4}, {2048, 512, 4}, {4096, 512, 4},
 };
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int, int>, Launch> g_tuned;
@@ -1482,17 +1842,23 @@ int tune_launch(SolveSet& S, const double* val64, const double* b, double* x, co
     if ((long)L.tile * 2 > (long)S.N && L.tile != kCandidates[0].tile) continue;
     if (int r = build_tiles(S, L.tile)) return r;
     if (L.rows == 3 && !Ops<V, W, I>::lds_fits(S)) continue;
+    if (L.rows == kResident && !Ops<V, W, I>::resident_fits(S, L)) continue;
     const auto a = make_args<V, W, I>(S, val64, b, x);
     Ops<V, W, I>::start(S, a, ot, L, s);
     Ops<V, W, I>::spmv(S, a, L, s);
-    for (int w = 0; w < 4; ++w)  // warm caches and clocks
-      Ops<V, W, I>::iter(S, a, w & 1, 1, L, s, 0.0);
+    const bool res = L.rows == kResident;
+    // warm caches and clocks
+    if (res) Ops<V, W, I>::resident(S, a, 1, 5, L, s, 0.0);
+    else
+      for (int w = 0; w < 4; ++w) Ops<V, W, I>::iter(S, a, w & 1, 1, L, s, 0.0);
     // best of three rounds of twenty iterations: single rounds vary by a few
     // per cent, as much as neighbouring shapes differ
     float ms = 1e30f;
     for (int round = 0; round < 3; ++round) {
       PS_HIP(hipEventRecord(S.tev[0], s));
-      for (int w = 0; w < 20; ++w) Ops<V, W, I>::iter(S, a, w & 1, 1, L, s, 0.0);
+      if (res) Ops<V, W, I>::resident(S, a, 1, 21, L, s, 0.0);
+      else
+        for (int w = 0; w < 20; ++w) Ops<V, W, I>::iter(S, a, w & 1, 1, L, s, 0.0);
       PS_HIP(hipEventRecord(S.tev[1], s));
       PS_HIP(hipEventSynchronize(S.tev[1]));
       float r = 0.f;
@@ -1525,6 +1891,11 @@ int run(SolveSet& S, const double* val64, const double* b, double* x, const pm_o
   if (int r = build_tiles(S, L.tile)) return r;
   if (L.rows == 3 && !O::lds_fits(S)) {
     set_error(PM_INVALID_ARG, "the tile's column window does not fit the LDS of one block");
+    return PM_INVALID_ARG;
+  }
+  if (L.rows == kResident && !O::resident_fits(S, L)) {
+    set_error(PM_INVALID_ARG,
+              "the resident schedule needs one system whose tiles all fit the device at once");
     return PM_INVALID_ARG;
   }
   const auto a = make_args<V, W, I>(S, val64, b, x);
@@ -1630,13 +2001,16 @@ int set_init(SolveSet& S, const std::vector<int>& rows, int64_t nnz, int index_b
   int r;
   if ((r = salloc(S, &S.tile_sys, T)) || (r = salloc(S, &S.tile_r0, T)) ||
       (r = salloc(S, &S.tile_r1, T)) || (r = salloc(S, &S.sys_tile0, S.n_sys + 1)) ||
-      (r = salloc(S, &S.tile_lo, T)) || (r = salloc(S, &S.tile_hi, T)))
+      (r = salloc(S, &S.tile_lo, T)) || (r = salloc(S, &S.tile_hi, T)) ||
+      (r = salloc(S, &S.tile_pub_lo, T)) || (r = salloc(S, &S.tile_pub_hi, T)))
     return r;
   {
-    int dev = 0, lim = 0;
+    int dev = 0, lim = 0, ncu = 0;
     PS_HIP(hipGetDevice(&dev));
     PS_HIP(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    PS_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     S.lds_limit = lim;
+    S.n_cu = ncu;
   }
   double* d;
   int32_t* i32;
@@ -1696,17 +2070,25 @@ int time_kernel(SolveSet& S, int which, int n_launch, hipStream_t s, double* ms)
   k_timing_state<<<(S.n_sys + 63) / 64, 64, 0, s>>>(S.ss, S.n_sys);
   Ops<V, W, I>::spmv(S, a, L, s);  // partials for the first fused iteration
   PS_HIP(hipEventRecord(S.tev[0], s));
-  for (int r = 0; r < n_launch; ++r) {
-    if (which == 0) Ops<V, W, I>::spmv(S, a, L, s);
-    else if (which == 1) Ops<V, W, I>::iter(S, a, r & 1, 1, L, s, 0.0);
-    else k_resid<V, W, I><<<S.n_tiles, L.block, 0, s>>>(a, 2, 0.0);
+  // the resident kernel is timed as the solve runs it: launches of m - 1
+  // iterations (m of the last solve); the time returned is per iteration
+  const bool res = which == 1 && L.rows == kResident;
+  const int per = res ? std::max(1, S.g_m - 1) : 1;
+  if (res) {
+    for (int r = 0; r < n_launch; ++r) Ops<V, W, I>::resident(S, a, 1, 1 + per, L, s, 0.0);
+  } else {
+    for (int r = 0; r < n_launch; ++r) {
+      if (which == 0) Ops<V, W, I>::spmv(S, a, L, s);
+      else if (which == 1) Ops<V, W, I>::iter(S, a, r & 1, 1, L, s, 0.0);
+      else k_resid<V, W, I><<<S.n_tiles, L.block, 0, s>>>(a, 2, 0.0);
+    }
   }
   PS_HIP(hipEventRecord(S.tev[1], s));
   PS_HIP(hipGetLastError());
   PS_HIP(hipEventSynchronize(S.tev[1]));
   float t = 0.f;
   PS_HIP(hipEventElapsedTime(&t, S.tev[0], S.tev[1]));
-  *ms = (double)t / n_launch;
+  *ms = (double)t / ((double)n_launch * per);
   return PM_OK;
 }
 }  // namespace

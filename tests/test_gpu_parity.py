@@ -205,7 +205,8 @@ def test_solves_are_deterministic_and_launch_shape_independent():
         xr, ir = B().pcg_solve(c["mesh"], val, b, precision=prec)
         for tile, block, shape in ((256, 256, 1), (768, 64, 2), (4096, 512, 1), (1024, 256, -1),
                                    (512, 128, -1), (2048, 256, 2), (1024, 192, 1), (1024, 256, 3),
-                                   (2048, 512, 3), (300, 64, 3)):
+                                   (2048, 512, 3), (300, 64, 3), (1024, 256, 4), (2048, 256, 4),
+                                   (300, 64, 4)):
             x3, i3 = B().pcg_solve(c["mesh"], val, b, precision=prec, tile_rows=tile, block=block,
                                    iter_shape=shape)
             assert i3["status"] == 0
@@ -229,6 +230,43 @@ def test_lds_staged_iteration_is_bitwise_the_gather_one():
             x3, i3 = B().pcg_solve(c["mesh"], val, b, precision=prec, tile_rows=tile, block=block,
                                    iter_shape=3)
             assert i1["status"] == 0 and torch.equal(x1, x3) and i1["iters"] == i3["iters"]
+
+
+def test_resident_chunk_is_bitwise_the_lds_one():
+    """The resident chunk kernel (iter_shape 4: a chunk's m - 1 iterations in
+    one launch, the tiles' rows held on chip, a grid barrier between
+    iterations) gives bitwise the solutions and iteration counts of the
+    LDS-staged kernel at the same tiles: both precisions, tiles of 4 and 8
+    rows per thread, chunks of 50, 7, 2 and 1 iterations, and an iteration
+    limit that stops inside a chunk."""
+    for name in ("chan", "aniso"):
+        c = case(name)
+        w = c["w"]
+        val = B().assemble_corrector(c["mesh"], B().PM_CP2, c["prm"], w["nu"], w["dt"])["val64"]
+        b = torch.tensor(w["rhs"]["cp2"], device=c["dev"])
+        for prec in (0, 1):
+            for tile, block in ((1024, 256), (2048, 256), (2048, 512), (512, 128)):
+                for m in (50, 7, 2, 1):
+                    kw = dict(precision=prec, tile_rows=tile, block=block, replace_every=m)
+                    x3, i3 = B().pcg_solve(c["mesh"], val, b, iter_shape=3, **kw)
+                    x4, i4 = B().pcg_solve(c["mesh"], val, b, iter_shape=4, **kw)
+                    assert i3["status"] == 0 and i4["status"] == 0
+                    assert i3["iters"] == i4["iters"] and torch.equal(x3, x4), (name, prec, tile, block, m)
+            kw = dict(precision=prec, tile_rows=2048, block=256, max_it=73)
+            x3, i3 = B().pcg_solve(c["mesh"], val, b, iter_shape=3, **kw)
+            x4, i4 = B().pcg_solve(c["mesh"], val, b, iter_shape=4, **kw)
+            assert i3["status"] == i4["status"] == B().PM_MAXIT
+            assert i3["iters"] == i4["iters"] and torch.equal(x3, x4)
+    # more than eight rows per thread is not a resident shape
+    c = case("chan")
+    w = c["w"]
+    val = B().assemble_corrector(c["mesh"], B().PM_CP2, c["prm"], w["nu"], w["dt"])["val64"]
+    b = torch.tensor(w["rhs"]["cp2"], device=c["dev"])
+    with pytest.raises(B().PMError) as e:
+        B().pcg_solve(c["mesh"], val, b, tile_rows=4096, block=256, iter_shape=4)
+    assert e.value.status == B().PM_INVALID_ARG
+    x, info = B().pcg_solve(c["mesh"], val, b, tile_rows=2048, block=256, iter_shape=4)
+    assert info["status"] == 0
 
 
 def test_error_statuses():

@@ -117,6 +117,22 @@ def test_channel_1M_assembly_and_solves(kind):
             assert abs(info["iters"] - io["iters"]) <= max(50, 0.02 * io["iters"])
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_channel_1M_resident_chunk_is_bitwise_the_lds_one(precision):
+    """At full size (245 tiles of 4096 rows, one per compute unit) the resident
+    chunk kernel reproduces the LDS-staged schedule bit for bit."""
+    c = channel_case(276, 2, False)
+    w = c["w"]
+    val = B().assemble_corrector(c["mesh"], KIND["cp2"], c["prm"], w["nu"], w["dt"])["val64"]
+    bt = torch.tensor(w["rhs"]["cp2"], device=c["dev"])
+    kw = dict(precision=precision, tile_rows=4096, block=512)
+    x3, i3 = B().pcg_solve(c["mesh"], val, bt, iter_shape=3, **kw)
+    x4, i4 = B().pcg_solve(c["mesh"], val, bt, iter_shape=4, **kw)
+    log(f"precision {precision}: LDS {i3['iters']} iterations, resident {i4['iters']}")
+    assert i3["status"] == 0 and i4["status"] == 0
+    assert i3["iters"] == i4["iters"] and torch.equal(x3, x4)
+
+
 def test_aniso_channel_4M_structure_and_residual():
     c = dict(channel_case(552, 3, True), key=(552, 3, True))
     w = c["w"]
