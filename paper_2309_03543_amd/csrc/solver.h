@@ -27,7 +27,6 @@ struct SysState {
   int32_t status;           // PM_* status once stopped
   int32_t k_best;           // iteration at which res2 last fell below best_res2 / 4
   int32_t err;              // input check failure found by the preparation kernel
-  uint32_t bar;             // arrivals at the grid barrier of the resident chunk kernel
 };
 
 // A set of one or more independent systems laid out one after another.
@@ -52,6 +51,9 @@ struct SolveSet {
   int *tile_pub_lo = nullptr, *tile_pub_hi = nullptr;
   int win_max = 0;
   int n_cu = 0;       // compute units of the device (queried once)
+  // resident chunk kernel: per tile, at a 64-byte stride, the number of
+  // iterations whose results the tile has published in the current launch
+  uint32_t* flags = nullptr;
   int lds_limit = 0;  // bytes of LDS one block may use (queried once)
   // workspace: difference-form rows, vectors, partials, states
   void *c = nullptr, *w = nullptr, *idx = nullptr;

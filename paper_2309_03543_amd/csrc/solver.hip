@@ -76,6 +76,7 @@ struct SetArgs {
   V* y;             // D'^{-1} r (Chebyshev schedule)
   V* zc[3];         // Chebyshev iterates, rotating
   SysState* ss;
+  uint32_t* flags;  // [tile * 16]: resident chunk kernel's published-iteration counts
 };
 
 // Fixed-order sum over the tile partials t0..t1-1 (stride 4); every thread of
@@ -848,28 +849,39 @@ __device__ __forceinline__ void st_agent(T* p, T x) {
                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Grid barrier of the resident chunk kernel: each wave waits until its own
-// stores have completed, then the block adds one arrival to *ctr and waits
-// until all `target` arrivals of this barrier are in.  The wait is bounded
+// Grid barrier of the resident chunk kernel.  Each wave waits until its own
+// stores (halo rows, tile partials) have completed; then the block publishes
+// the count of iterations it has finished in its own flag (a 64-byte slot of
+// `flags`), and its threads poll the flags of all nt tiles, one flag per
+// thread, until every tile has published `count`.  No atomics: a shared
+// counter would serialise the arrivals of all blocks.  Every wait is bounded
 // (about a second): a grid that is not fully resident ends with an error
 // instead of spinning for ever.
-__device__ __forceinline__ bool grid_barrier(uint32_t* ctr, uint32_t target) {
-  __shared__ int ok;
+__device__ __forceinline__ bool grid_barrier(uint32_t* flags, int t, int nt, uint32_t count) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    int spins = 0;
+  if (threadIdx.x == 0)
+    __hip_atomic_store(flags + 16 * (size_t)t, count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  int good = 1;
+  for (int u = (int)threadIdx.x; u < nt; u += blockDim.x) {
     constexpr int kMaxSpins = 1 << 20;
-    while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target &&
+    int spins = 0;
+    while (__hip_atomic_load(flags + 16 * (size_t)u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+               count &&
            spins < kMaxSpins) {
       __builtin_amdgcn_s_sleep(1);
       ++spins;
     }
-    ok = spins < kMaxSpins;
+    good &= spins < kMaxSpins;
   }
-  __syncthreads();
-  return ok != 0;
+  return __syncthreads_and(good) != 0;
+}
+
+// Clears the resident kernel's flags before a launch (a kernel, not a memset,
+// so that it can sit in a captured graph).
+__global__ void k_flags_reset(uint32_t* flags, int nt) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < nt) flags[16 * (size_t)t] = 0u;
 }
 
 // partial_reduce over all nt tiles with device-coherent loads (same order)
@@ -913,8 +925,6 @@ __device__ __forceinline__ void tile_partial_agent(double (&v)[4], double* part)
   }
 }
 
-__global__ void k_bar_reset(SysState* ss) { ss[0].bar = 0u; }
-
 // Resident chunk kernel: iterations j0 .. j1-1 of a chunk of one system in
 // one launch, with one block per tile and every block resident (the host
 // launches it only when the whole grid fits the device at once).  Each
@@ -947,12 +957,16 @@ __global__ void __launch_bounds__(512) k_chunk(SetArgs<V, W, I> a, int j0, int j
   V* __restrict__ lp = reinterpret_cast<V*>(lds_raw);
   V* __restrict__ lz = lp + nwin;
   V* __restrict__ lq = lz + nwin;  // q~ of the tile's own rows
+  // 16-bit column offsets of the tile's rows live in LDS ([3][RPT * B]),
+  // wider ones in registers
+  constexpr bool kIdxLds = sizeof(I) == 2;
+  I* __restrict__ lx = reinterpret_cast<I*>(lq + RPT * B);
   // halo: window rows below the tile (nlow of them), then above it
   const int nlow = r0 - lo, nhalo = nwin - (r1 - r0);
   auto halo_w = [&](int h) { return h < nlow ? h : h + (r1 - r0); };
 
   W w0[RPT], w1[RPT], w2[RPT], cc[RPT];
-  I i0[RPT], i1[RPT], i2[RPT];
+  I i0[kIdxLds ? 1 : RPT], i1[kIdxLds ? 1 : RPT], i2[kIdxLds ? 1 : RPT];
   V xa[RPT];
 #pragma unroll
   for (int u = 0; u < RPT; ++u) {
@@ -961,9 +975,16 @@ __global__ void __launch_bounds__(512) k_chunk(SetArgs<V, W, I> a, int j0, int j
     w0[u] = a.w[i];
     w1[u] = a.w[N + i];
     w2[u] = a.w[2 * N + i];
-    i0[u] = a.idx[i];
-    i1[u] = a.idx[N + i];
-    i2[u] = a.idx[2 * N + i];
+    if constexpr (kIdxLds) {
+      const int l = tid + u * B;
+      lx[l] = a.idx[i];
+      lx[RPT * B + l] = a.idx[N + i];
+      lx[2 * RPT * B + l] = a.idx[2 * N + i];
+    } else {
+      i0[u] = a.idx[i];
+      i1[u] = a.idx[N + i];
+      i2[u] = a.idx[2 * N + i];
+    }
     cc[u] = a.c[i];
     xa[u] = a.xacc[i];
   }
@@ -975,7 +996,7 @@ __global__ void __launch_bounds__(512) k_chunk(SetArgs<V, W, I> a, int j0, int j
   int src = (j0 - 1) & 1;
   for (int j = j0; j < j1; ++j, src ^= 1) {
     const bool first = j == j0, last = j + 1 == j1;
-    if (!first && !grid_barrier(&S.bar, (uint32_t)(++nbar) * (uint32_t)nt)) {
+    if (!first && !grid_barrier(a.flags, t, nt, (uint32_t)(++nbar))) {
       failed = true;
       break;
     }
@@ -987,7 +1008,7 @@ __global__ void __launch_bounds__(512) k_chunk(SetArgs<V, W, I> a, int j0, int j
     V* __restrict__ qd = a.q[src ^ 1];
     // the first halo rows of this thread are in flight while the partials
     // are reduced
-    constexpr int HR = 2;
+    constexpr int HR = sizeof(V) == 8 ? 2 : 4;
     V hp[HR], hz[HR], hq[HR];
 #pragma unroll
     for (int u = 0; u < HR; ++u) {
@@ -1062,10 +1083,21 @@ __global__ void __launch_bounds__(512) k_chunk(SetArgs<V, W, I> a, int j0, int j
       if (i >= r1) continue;
       const int li = i - lo;
       const double pi = (double)lp[li], zi = (double)lz[li], ci = (double)cc[u];
+      I o0, o1, o2;
+      if constexpr (kIdxLds) {
+        const int l = tid + u * B;
+        o0 = lx[l];
+        o1 = lx[RPT * B + l];
+        o2 = lx[2 * RPT * B + l];
+      } else {
+        o0 = i0[u];
+        o1 = i1[u];
+        o2 = i2[u];
+      }
       double y = ci * pi;
-      y += (double)w0[u] * (pi - (double)lp[col_of<I>(i, i0[u]) - lo]);
-      y += (double)w1[u] * (pi - (double)lp[col_of<I>(i, i1[u]) - lo]);
-      y += (double)w2[u] * (pi - (double)lp[col_of<I>(i, i2[u]) - lo]);
+      y += (double)w0[u] * (pi - (double)lp[col_of<I>(i, o0) - lo]);
+      y += (double)w1[u] * (pi - (double)lp[col_of<I>(i, o1) - lo]);
+      y += (double)w2[u] * (pi - (double)lp[col_of<I>(i, o2) - lo]);
       const double d = ((ci + (double)w0[u]) + (double)w1[u]) + (double)w2[u];
       const V qn = (V)(y / d);
       lq[i - r0] = qn;
@@ -1622,6 +1654,7 @@ SetArgs<V, W, I> make_args(SolveSet& S, const double* val, const double* b, doub
   a.y = (V*)S.y;
   for (int k = 0; k < 3; ++k) a.zc[k] = (V*)S.zc[k];
   a.ss = S.ss;
+  a.flags = S.flags;
   return a;
 }
 
@@ -1722,13 +1755,16 @@ struct Ops {
   }
   // whether every tile of the current set can be resident at once (one system,
   // its window in LDS, the whole grid on the device together)
-  static size_t resident_lds_bytes(const SolveSet& S) {
-    return sizeof(V) * (2 * (size_t)S.win_max + (size_t)S.tile_rows);
+  // LDS of the resident kernel: p and z of the window, q~ of the tile's
+  // RPT * block row slots, and 16-bit column offsets of those rows
+  static size_t resident_lds_bytes(const SolveSet& S, const Launch& L) {
+    const size_t slots = (size_t)resident_rpt(L.tile, L.block) * L.block;
+    return sizeof(V) * (2 * (size_t)S.win_max + slots) + (sizeof(I) == 2 ? 3 * 2 * slots : 0);
   }
   static bool resident_fits(const SolveSet& S, const Launch& L) {
     const int rpt = resident_rpt(L.tile, L.block);
     if (S.n_sys != 1 || rpt == 0 || S.n_cu <= 0) return false;
-    const size_t need = resident_lds_bytes(S);
+    const size_t need = resident_lds_bytes(S, L);
     if (need > (size_t)S.lds_limit) return false;
     const void* f = resident_fn(rpt);
     if (need > 65536 &&
@@ -1747,8 +1783,8 @@ struct Ops {
   // iterations j0 .. j1-1 of a chunk in one resident launch (buffer (j0-1)&1 in)
   static void resident(SolveSet& S, const A& a, int j0, int j1, const Launch& L, hipStream_t s,
                        double scale) {
-    k_bar_reset<<<1, 1, 0, s>>>(S.ss);
-    const size_t lds = resident_lds_bytes(S);
+    k_flags_reset<<<(S.n_tiles + 255) / 256, 256, 0, s>>>(S.flags, S.n_tiles);
+    const size_t lds = resident_lds_bytes(S, L);
     if (resident_rpt(L.tile, L.block) == 4)
       k_chunk<V, W, I, 4><<<S.n_tiles, L.block, lds, s>>>(a, j0, j1, scale);
     else
@@ -2030,7 +2066,8 @@ int set_init(SolveSet& S, const std::vector<int>& rows, int64_t nnz, int index_b
     *v = d;
   }
   if ((r = salloc(S, &S.part[0], 4 * T)) || (r = salloc(S, &S.part[1], 4 * T)) ||
-      (r = salloc(S, &S.part3, 4 * T)) || (r = salloc(S, &S.ss, (size_t)S.n_sys)))
+      (r = salloc(S, &S.part3, 4 * T)) || (r = salloc(S, &S.ss, (size_t)S.n_sys)) ||
+      (r = salloc(S, &S.flags, 16 * T)))
     return r;
   PS_HIP(hipHostMalloc((void**)&S.h_ss, 3 * sizeof(SysState) * S.n_sys, hipHostMallocDefault));
   PS_HIP(hipStreamCreateWithFlags(&S.cap, hipStreamNonBlocking));
