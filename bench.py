@@ -303,6 +303,19 @@ def main():
             roof["note"] = ("achieved = the iterations' algorithmic bytes (what a streaming "
                             "iteration moves) over the launch time; the resident kernel keeps "
                             "its tiles on chip, so traffic is the bytes it actually moves")
+            # the streaming form of the same iteration (LDS-staged fused kernel,
+            # same tiles), which is bound by HBM: its fraction of the roofline
+            sl = {"tile_rows": launch["tile_rows"], "block": launch["block"], "iter_shape": 3}
+            v2 = B.assemble_corrector(tmesh, B.PM_CP2, prm0, w0["nu"], w0["dt"])["val64"]
+            B.pcg_solve(tmesh, v2, rhs[0]["cp2"], **sl)
+            ms_s, by_s = B.pm_time_kernel(tmesh, 1, 200)
+            roof["streaming_kernel"] = {
+                "kernel": "k_iter_lds", "launch": sl, "ms_per_launch": ms_s,
+                "bytes_per_launch": by_s, "achieved": by_s / ms_s / 1e6,
+                "frac": by_s / ms_s / 1e6 / HBM_PEAK_GBS,
+                "traffic": measured_traffic(wname, sl, "k_iter")}
+            log(f"  streaming form (k_iter_lds): {ms_s * 1e3:.2f} us per iteration, "
+                f"{by_s / ms_s / 1e6:.0f} GB/s ({by_s / ms_s / 1e6 / HBM_PEAK_GBS:.1%} of HBM peak)")
     else:
         roof = None
 

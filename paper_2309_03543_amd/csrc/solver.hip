@@ -851,9 +851,12 @@ __device__ __forceinline__ void st_agent(T* p, T x) {
 
 // Grid barrier of the resident chunk kernel.  Each wave waits until its own
 // stores (halo rows, tile partials) have completed; then the block publishes
-// the count of iterations it has finished in its own flag (a 64-byte slot of
+// `count` (the solve's iteration number it has just finished: increasing
+// within a solve, reset at its start) in its own flag (a 64-byte slot of
 // `flags`), and its threads poll the flags of all nt tiles, one flag per
-// thread, until every tile has published `count`.  No atomics: a shared
+// thread, until every tile has published at least `count`.  A tile one
+// iteration ahead wrote the other buffer parity, so its data does not
+// disturb this iteration's.  No atomics: a shared
 // counter would serialise the arrivals of all blocks.  Every wait is bounded
 // (about a second): a grid that is not fully resident ends with an error
 // instead of spinning for ever.
@@ -877,8 +880,8 @@ __device__ __forceinline__ bool grid_barrier(uint32_t* flags, int t, int nt, uin
   return __syncthreads_and(good) != 0;
 }
 
-// Clears the resident kernel's flags before a launch (a kernel, not a memset,
-// so that it can sit in a captured graph).
+// Clears the resident kernel's flags at the start of a solve (a kernel, not a
+// memset, so that it can sit in a captured graph).
 __global__ void k_flags_reset(uint32_t* flags, int nt) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < nt) flags[16 * (size_t)t] = 0u;
@@ -991,12 +994,11 @@ __global__ void __launch_bounds__(512) k_chunk(SetArgs<V, W, I> a, int j0, int j
   const bool first_block = t == 0 && tid == 0;
   double al = 0.0, be = 0.0, rho = 0.0;
   int k_done = -1;
-  int nbar = 0;
   bool failed = false;
   int src = (j0 - 1) & 1;
   for (int j = j0; j < j1; ++j, src ^= 1) {
     const bool first = j == j0, last = j + 1 == j1;
-    if (!first && !grid_barrier(a.flags, t, nt, (uint32_t)(++nbar))) {
+    if (!first && !grid_barrier(a.flags, t, nt, (uint32_t)(S.iter_base + j - 1))) {
       failed = true;
       break;
     }
@@ -1697,7 +1699,11 @@ constexpr int kResident = 4;
 template <typename V, typename W, typename I>
 struct Ops {
   using A = SetArgs<V, W, I>;
+  static void flags_reset(SolveSet& S, hipStream_t s) {
+    k_flags_reset<<<(S.n_tiles + 255) / 256, 256, 0, s>>>(S.flags, S.n_tiles);
+  }
   static void start(SolveSet& S, const A& a, const pm_opts& o, const Launch& L, hipStream_t s) {
+    if (L.rows == kResident) flags_reset(S, s);
     const int checks = o.stag_checks > 0 ? o.stag_checks : 40;
     const long win = (long)checks * o.replace_every;
     k_sys_init<<<(S.n_sys + 63) / 64, 64, 0, s>>>(S.ss, S.n_sys, o.max_it,
@@ -1783,7 +1789,6 @@ struct Ops {
   // iterations j0 .. j1-1 of a chunk in one resident launch (buffer (j0-1)&1 in)
   static void resident(SolveSet& S, const A& a, int j0, int j1, const Launch& L, hipStream_t s,
                        double scale) {
-    k_flags_reset<<<(S.n_tiles + 255) / 256, 256, 0, s>>>(S.flags, S.n_tiles);
     const size_t lds = resident_lds_bytes(S, L);
     if (resident_rpt(L.tile, L.block) == 4)
       k_chunk<V, W, I, 4><<<S.n_tiles, L.block, lds, s>>>(a, j0, j1, scale);
@@ -1883,7 +1888,8 @@ int tune_launch(SolveSet& S, const double* val64, const double* b, double* x, co
     Ops<V, W, I>::start(S, a, ot, L, s);
     Ops<V, W, I>::spmv(S, a, L, s);
     const bool res = L.rows == kResident;
-    // warm caches and clocks
+    // warm caches and clocks (the resident kernel's iteration numbers keep
+    // increasing from launch to launch, as in a solve)
     if (res) Ops<V, W, I>::resident(S, a, 1, 5, L, s, 0.0);
     else
       for (int w = 0; w < 4; ++w) Ops<V, W, I>::iter(S, a, w & 1, 1, L, s, 0.0);
@@ -1892,7 +1898,7 @@ int tune_launch(SolveSet& S, const double* val64, const double* b, double* x, co
     float ms = 1e30f;
     for (int round = 0; round < 3; ++round) {
       PS_HIP(hipEventRecord(S.tev[0], s));
-      if (res) Ops<V, W, I>::resident(S, a, 1, 21, L, s, 0.0);
+      if (res) Ops<V, W, I>::resident(S, a, 5 + 20 * round, 25 + 20 * round, L, s, 0.0);
       else
         for (int w = 0; w < 20; ++w) Ops<V, W, I>::iter(S, a, w & 1, 1, L, s, 0.0);
       PS_HIP(hipEventRecord(S.tev[1], s));
@@ -2105,6 +2111,7 @@ int time_kernel(SolveSet& S, int which, int n_launch, hipStream_t s, double* ms)
   const auto a = make_args<V, W, I>(S, S.last_val, nullptr, nullptr);
   const Launch L = {S.last_tile, S.last_block, S.last_rows};
   k_timing_state<<<(S.n_sys + 63) / 64, 64, 0, s>>>(S.ss, S.n_sys);
+  if (L.rows == kResident) Ops<V, W, I>::flags_reset(S, s);
   Ops<V, W, I>::spmv(S, a, L, s);  // partials for the first fused iteration
   PS_HIP(hipEventRecord(S.tev[0], s));
   // the resident kernel is timed as the solve runs it: launches of m - 1
@@ -2112,7 +2119,8 @@ int time_kernel(SolveSet& S, int which, int n_launch, hipStream_t s, double* ms)
   const bool res = which == 1 && L.rows == kResident;
   const int per = res ? std::max(1, S.g_m - 1) : 1;
   if (res) {
-    for (int r = 0; r < n_launch; ++r) Ops<V, W, I>::resident(S, a, 1, 1 + per, L, s, 0.0);
+    for (int r = 0; r < n_launch; ++r)
+      Ops<V, W, I>::resident(S, a, 1 + r * per, 1 + (r + 1) * per, L, s, 0.0);
   } else {
     for (int r = 0; r < n_launch; ++r) {
       if (which == 0) Ops<V, W, I>::spmv(S, a, L, s);
