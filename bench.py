@@ -64,14 +64,19 @@ def cpu_model() -> str:
 
 
 def source_digest() -> str:
-    """Digest of the kernel sources, to tell whether stored counter readings
-    still describe the kernels in this tree."""
+    """Digest of the kernel sources with comments and blank lines removed, to
+    tell whether stored counter readings still describe the kernels in this
+    tree (editing a comment does not change a kernel)."""
     import hashlib
+    import re
 
     h = hashlib.sha256()
     for f in ("solver.hip", "kernels.h", "solver.h"):
-        with open(os.path.join(ROOT, "paper_2309_03543_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2309_03543_amd", "csrc", f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        code = [ln.split("//", 1)[0].rstrip() for ln in text.splitlines()]
+        h.update("\n".join(ln for ln in code if ln.strip()).encode())
     return h.hexdigest()[:16]
 
 

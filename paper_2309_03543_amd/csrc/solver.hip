@@ -13,10 +13,14 @@
 // A chunk of m iterations opens with a plain product (k_spmv) and ends with
 // the m-th update folding the increments into the double-double solution
 // (k_update_flush), an exact float64 residual from the CSR matrix (k_resid,
-// k_sys_check) and the new direction (k_pdir).  The kernel boundaries are the
-// only grid-wide synchronisation: no fences, no spin waits.  Chunks are
-// captured once in a HIP graph and replayed; a system whose test passes is
-// masked out of later kernels.
+// k_sys_check) and the new direction (k_pdir).  Between them the per-iteration
+// kernels synchronise only through kernel boundaries: no fences, no spin
+// waits.  Where every tile of one system fits the device at once, the
+// resident chunk kernel (k_chunk) instead runs the chunk's m - 1 iterations
+// in one launch, holding each tile's rows on chip and separating iterations
+// with a bounded grid barrier on per-tile flags.  Chunks are captured once in
+// a HIP graph and replayed; a system whose test passes is masked out of later
+// kernels.
 //
 // Difference form: row i is stored as c_i = sum_j a_ij (its mass or
 // Dirichlet part) and w_ij = -a_ij, and (A p)_i = c_i p_i + sum_j w_ij (p_i -

@@ -9,6 +9,7 @@ Tolerances
     float64 solution; iteration counts within one replacement period.
 """
 import functools
+import math
 
 import numpy as np
 import pytest
@@ -269,6 +270,31 @@ def test_resident_chunk_is_bitwise_the_lds_one():
     assert info["status"] == 0
 
 
+def test_kernel_timing_hook_on_every_schedule():
+    """pm_time_kernel times the last solve's kernels and returns the bytes its
+    header documents; on the resident schedule it times chunk-length launches
+    and returns the time per iteration.  Solves after the timing give the
+    same answer as before it."""
+    c = case("chan")
+    w = c["w"]
+    val = B().assemble_corrector(c["mesh"], B().PM_CP2, c["prm"], w["nu"], w["dt"])["val64"]
+    b = torch.tensor(w["rhs"]["cp2"], device=c["dev"])
+    n = c["geo"]["n"]
+    for prec, sv in ((0, 8), (1, 4)):
+        for shape in (-1, 1, 3, 4):
+            kw = dict(precision=prec, tile_rows=2048, block=256, iter_shape=shape)
+            x1, i1 = B().pcg_solve(c["mesh"], val, b, **kw)
+            for which, reps in ((0, 20), (1, 4), (2, 5)):
+                ms, by = B().pm_time_kernel(c["mesh"], which, reps)
+                assert math.isfinite(ms) and 0.0 < ms < 50.0
+                if which == 0:
+                    assert by == n * (4 * sv + 3 * 2 + 3 * sv)
+                elif which == 1:
+                    assert by == n * (4 * sv + 3 * 2 + (10 if shape == -1 else 8) * sv)
+            x2, i2 = B().pcg_solve(c["mesh"], val, b, **kw)
+            assert torch.equal(x1, x2) and i1["iters"] == i2["iters"]
+
+
 def test_error_statuses():
     Bm = B()
     c = case("tiny")
@@ -324,7 +350,8 @@ def test_wide_column_offsets_match_narrow_bitwise():
     val = B().assemble_corrector(mesh, B().PM_CP2, c["prm"], w["nu"], w["dt"])["val64"]
     b = torch.tensor(w["rhs"]["cp2"], device=c["dev"])
     shapes = [dict(tile_rows=1024, block=256, iter_shape=1), dict(tile_rows=2048, block=256, iter_shape=2),
-              dict(tile_rows=2048, block=512, iter_shape=3), dict(tile_rows=1024, block=256, iter_shape=-1)]
+              dict(tile_rows=2048, block=512, iter_shape=3), dict(tile_rows=1024, block=256, iter_shape=-1),
+              dict(tile_rows=2048, block=256, iter_shape=4), dict(tile_rows=1024, block=256, iter_shape=4)]
     runs = []
     try:
         for bits in (16, 32):
