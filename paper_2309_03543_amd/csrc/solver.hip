@@ -995,6 +995,19 @@ __global__ void __launch_bounds__(512) k_chunk(SetArgs<V, W, I> a, int j0, int j
     cc[u] = a.c[i];
     xa[u] = a.xacc[i];
   }
+  // own rows' p, z, q~ of the chunk's first iteration, from the buffer the
+  // previous kernels wrote, into LDS (later iterations keep them there)
+  {
+    const int src0 = (j0 - 1) & 1;
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+      const int i = r0 + tid + u * B;
+      if (i >= r1) continue;
+      lp[i - lo] = a.p[src0][i];
+      lz[i - lo] = a.z[src0][i];
+      lq[i - r0] = a.q[src0][i];
+    }
+  }
   const bool first_block = t == 0 && tid == 0;
   double al = 0.0, be = 0.0, rho = 0.0;
   int k_done = -1;
@@ -1014,7 +1027,7 @@ __global__ void __launch_bounds__(512) k_chunk(SetArgs<V, W, I> a, int j0, int j
     V* __restrict__ qd = a.q[src ^ 1];
     // the first halo rows of this thread are in flight while the partials
     // are reduced
-    constexpr int HR = sizeof(V) == 8 ? 2 : 4;
+    constexpr int HR = 4;
     V hp[HR], hz[HR], hq[HR];
 #pragma unroll
     for (int u = 0; u < HR; ++u) {
@@ -1040,17 +1053,17 @@ __global__ void __launch_bounds__(512) k_chunk(SetArgs<V, W, I> a, int j0, int j
     const double rn = rh - 2.0 * a_ * r[1] + a_ * a_ * r[2];
     const double b_ = rn / rh;
     const double as = a_ * scale, bs = b_ * scale;
-    // staging: the new z and p of the window into LDS; own rows by the
-    // thread that owns them, which also adds alpha p (old p) to x_acc.  The
-    // first iteration reads them from the buffer, later ones from LDS.
+    // staging: the new z and p of the window into LDS; own rows (old values
+    // in LDS) by the thread that owns them, which also adds alpha p (old p)
+    // to x_acc
 #pragma unroll
     for (int u = 0; u < RPT; ++u) {
       const int i = r0 + tid + u * B;
       if (i >= r1) continue;
       const int li = i - lo;
-      const V qold = first ? qs[i] : lq[i - r0];
-      const V pold = first ? ps[i] : lp[li];
-      const V zold = first ? zs[i] : lz[li];
+      const V qold = lq[i - r0];
+      const V pold = lp[li];
+      const V zold = lz[li];
       const V zn = (V)((double)zold - as * (double)qold);
       const V pn = (V)((double)zn + bs * (double)pold);
       xa[u] = (V)((double)xa[u] + as * (double)pold);
