@@ -149,7 +149,16 @@ typedef struct {
                             barrier between iterations (one system whose
                             tiles all fit the device at once, tile_rows at
                             most 8 x block; else PM_INVALID_ARG; pcg_solve
-                            only); ignored when the tuner decides */
+                            only).  Each barrier wait is bounded; if one
+                            gives up (the grid was not all resident, e.g.
+                            compute units held by another process), the
+                            solve restarts on schedule 3 (or 1) with the
+                            same tiles, which computes bitwise the same
+                            iterations, and pm_last_launch reports that
+                            schedule.  The environment variable
+                            PMCORR_RESIDENT_SPINS sets the bound in polls
+                            (default 2^20, about a second); ignored when the
+                            tuner decides */
 } pm_opts;
 
 typedef struct {

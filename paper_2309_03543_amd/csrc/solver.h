@@ -27,6 +27,7 @@ struct SysState {
   int32_t status;           // PM_* status once stopped
   int32_t k_best;           // iteration at which res2 last fell below best_res2 / 4
   int32_t err;              // input check failure found by the preparation kernel
+  int32_t bar_fail;         // a block of the resident chunk kernel gave up waiting
 };
 
 // A set of one or more independent systems laid out one after another.
@@ -54,6 +55,7 @@ struct SolveSet {
   // resident chunk kernel: per tile, at a 64-byte stride, the number of
   // iterations whose results the tile has published in the current launch
   uint32_t* flags = nullptr;
+  int resident_spins = 1 << 20;  // bound of each barrier wait (polls)
   int lds_limit = 0;  // bytes of LDS one block may use (queried once)
   // workspace: difference-form rows, vectors, partials, states
   void *c = nullptr, *w = nullptr, *idx = nullptr;
@@ -69,7 +71,7 @@ struct SolveSet {
   hipEvent_t ev[2] = {nullptr, nullptr};
   hipEvent_t tev[2] = {nullptr, nullptr};
   hipGraphExec_t graph = nullptr;
-  int g_prec = -1, g_m = -1, g_tile = -1, g_block = -1, g_rows = -1, g_pc = -1;
+  int g_prec = -1, g_m = -1, g_tile = -1, g_block = -1, g_rows = -1, g_pc = -1, g_spins = -1;
   const double* g_val = nullptr;
   // last solve, for the timing hook
   int last_prec = -1, last_tile = 0, last_block = 256, last_rows = 1, last_pc = 0;

@@ -862,24 +862,24 @@ __device__ __forceinline__ void st_agent(T* p, T x) {
 // iteration ahead wrote the other buffer parity, so its data does not
 // disturb this iteration's.  No atomics: a shared
 // counter would serialise the arrivals of all blocks.  Every wait is bounded
-// (about a second): a grid that is not fully resident ends with an error
-// instead of spinning for ever.
-__device__ __forceinline__ bool grid_barrier(uint32_t* flags, int t, int nt, uint32_t count) {
+// (max_spins polls, about a second by default): a grid that is not fully
+// resident gives up instead of spinning for ever.
+__device__ __forceinline__ bool grid_barrier(uint32_t* flags, int t, int nt, uint32_t count,
+                                             int max_spins) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0)
     __hip_atomic_store(flags + 16 * (size_t)t, count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   int good = 1;
   for (int u = (int)threadIdx.x; u < nt; u += blockDim.x) {
-    constexpr int kMaxSpins = 1 << 20;
     int spins = 0;
     while (__hip_atomic_load(flags + 16 * (size_t)u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
                count &&
-           spins < kMaxSpins) {
+           spins < max_spins) {
       __builtin_amdgcn_s_sleep(1);
       ++spins;
     }
-    good &= spins < kMaxSpins;
+    good &= spins < max_spins;
   }
   return __syncthreads_and(good) != 0;
 }
@@ -950,7 +950,7 @@ __device__ __forceinline__ void tile_partial_agent(double (&v)[4], double* part)
 // schedule.  RPT: rows per thread (RPT * blockDim >= tile rows).
 template <typename V, typename W, typename I, int RPT>
 __global__ void __launch_bounds__(512) k_chunk(SetArgs<V, W, I> a, int j0, int j1,
-                                               double scale) {
+                                               double scale, int max_spins) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const int t = xcd_block(blockIdx.x, gridDim.x);
   SysState& S = a.ss[0];
@@ -1015,7 +1015,7 @@ __global__ void __launch_bounds__(512) k_chunk(SetArgs<V, W, I> a, int j0, int j
   int src = (j0 - 1) & 1;
   for (int j = j0; j < j1; ++j, src ^= 1) {
     const bool first = j == j0, last = j + 1 == j1;
-    if (!first && !grid_barrier(a.flags, t, nt, (uint32_t)(S.iter_base + j - 1))) {
+    if (!first && !grid_barrier(a.flags, t, nt, (uint32_t)(S.iter_base + j - 1), max_spins)) {
       failed = true;
       break;
     }
@@ -1152,6 +1152,7 @@ __global__ void __launch_bounds__(512) k_chunk(SetArgs<V, W, I> a, int j0, int j
   }
   if (failed && tid == 0) {  // any block that gave up marks the solve failed
     S.status = PM_HIP_ERROR;
+    S.bar_fail = 1;
     S.done = 1;
   }
 }
@@ -1808,9 +1809,9 @@ struct Ops {
                        double scale) {
     const size_t lds = resident_lds_bytes(S, L);
     if (resident_rpt(L.tile, L.block) == 4)
-      k_chunk<V, W, I, 4><<<S.n_tiles, L.block, lds, s>>>(a, j0, j1, scale);
+      k_chunk<V, W, I, 4><<<S.n_tiles, L.block, lds, s>>>(a, j0, j1, scale, S.resident_spins);
     else
-      k_chunk<V, W, I, 8><<<S.n_tiles, L.block, lds, s>>>(a, j0, j1, scale);
+      k_chunk<V, W, I, 8><<<S.n_tiles, L.block, lds, s>>>(a, j0, j1, scale, S.resident_spins);
   }
   static void chunk(SolveSet& S, const A& a, int m, const Launch& L, hipStream_t s) {
     spmv(S, a, L, s);
@@ -1937,15 +1938,25 @@ int tune_launch(SolveSet& S, const double* val64, const double* b, double* x, co
 
 template <typename V, typename W, typename I>
 int run(SolveSet& S, const double* val64, const double* b, double* x, const pm_opts& o,
-        pm_info* infos, hipStream_t s) {
+        pm_info* infos, hipStream_t s, const Launch* force = nullptr) {
   using O = Ops<V, W, I>;
+  // bound of the resident kernel's barrier waits; PMCORR_RESIDENT_SPINS
+  // overrides it (a diagnostic knob: 0 makes every wait give up at once)
+  {
+    const char* e = std::getenv("PMCORR_RESIDENT_SPINS");
+    S.resident_spins = e ? std::max(0, std::atoi(e)) : 1 << 20;
+  }
   Launch L;
-  if (o.tile_rows > 0) {
+  bool tuned = false;
+  if (force) {
+    L = *force;
+  } else if (o.tile_rows > 0) {
     const int block = o.block > 0 ? std::min(512, std::max(64, (o.block / 64) * 64)) : 256;
     L = {std::max(kMinTile, o.tile_rows), block, o.iter_shape < 0 ? 0 : std::max(1, o.iter_shape)};
     if (o.precond == PM_PREC_CHEBYSHEV) L.rows = 1;  // the schedule applies to Jacobi only
   } else {
     if (int r = tune_launch<V, W, I>(S, val64, b, x, o, s, &L)) return r;
+    tuned = true;
   }
   if (int r = build_tiles(S, L.tile)) return r;
   if (L.rows == 3 && !O::lds_fits(S)) {
@@ -1973,7 +1984,8 @@ int run(SolveSet& S, const double* val64, const double* b, double* x, const pm_o
   PS_HIP(hipGetLastError());
 
   if (!S.graph || S.g_prec != o.precision || S.g_m != o.replace_every || S.g_tile != L.tile ||
-      S.g_block != L.block || S.g_rows != L.rows || S.g_pc != pc || S.g_val != val64) {
+      S.g_block != L.block || S.g_rows != L.rows || S.g_pc != pc || S.g_val != val64 ||
+      S.g_spins != S.resident_spins) {
     if (S.graph) {
       (void)hipGraphExecDestroy(S.graph);
       S.graph = nullptr;
@@ -1987,6 +1999,7 @@ int run(SolveSet& S, const double* val64, const double* b, double* x, const pm_o
     (void)hipGraphDestroy(g);
     S.g_prec = o.precision;
     S.g_m = o.replace_every;
+    S.g_spins = S.resident_spins;
     S.g_tile = L.tile;
     S.g_block = L.block;
     S.g_rows = L.rows;
@@ -2024,6 +2037,17 @@ int run(SolveSet& S, const double* val64, const double* b, double* x, const pm_o
   SysState* fin = S.h_ss + 2 * S.n_sys;
   PS_HIP(hipMemcpyAsync(fin, S.ss, bytes, hipMemcpyDeviceToHost, s));
   PS_HIP(hipStreamSynchronize(s));
+  // a resident launch whose grid was not all resident at once (a barrier
+  // wait gave up): solve again, from the start, on the streaming schedule
+  // with the same tiles, which computes bitwise the same iterations
+  if (L.rows == kResident && fin[0].bar_fail) {
+    const Launch L2 = {L.tile, L.block, O::lds_fits(S) ? 3 : 1};
+    if (tuned) {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      g_tuned[std::make_tuple(S.N, S.n_sys, o.precision, S.index_bits)] = L2;
+    }
+    return run<V, W, I>(S, val64, b, x, o, infos, s, &L2);
+  }
   int worst = PM_OK;
   for (int k = 0; k < S.n_sys; ++k) {
     const SysState& f = fin[k];
