@@ -280,8 +280,9 @@ def main():
     if tmesh is not None:
         launch = B.pm_last_launch(tmesh)
         fused = launch["iter_shape"] > 0
-        resident = launch["iter_shape"] == 4
-        it_name = "k_chunk" if resident else "k_iter" if fused else "k_update+k_spmv"
+        resident = launch["iter_shape"] in (4, 5)
+        it_name = ({4: "k_chunk", 5: "k_chunk_win"}.get(launch["iter_shape"])
+                   or ("k_iter" if fused else "k_update+k_spmv"))
         # the resident kernel runs a chunk's m - 1 = 49 iterations per launch
         per_launch = 49 if resident else 1
         for name, which, reps in (("k_spmv", 0, 200), (it_name, 1, 8 if resident else 200),

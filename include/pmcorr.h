@@ -157,8 +157,13 @@ typedef struct {
                             iterations, and pm_last_launch reports that
                             schedule.  The environment variable
                             PMCORR_RESIDENT_SPINS sets the bound in polls
-                            (default 2^20, about a second); ignored when the
-                            tuner decides */
+                            (default 2^20, about a second).  5 the resident
+                            window kernel: the same, for operators too large
+                            to hold on chip (one tile per compute unit):
+                            only each tile's column window of p and z stays
+                            in LDS, the matrix rows, x_acc and q~ are read
+                            every iteration.  Ignored when the tuner
+                            decides */
 } pm_opts;
 
 typedef struct {

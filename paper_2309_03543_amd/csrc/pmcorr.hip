@@ -216,7 +216,7 @@ namespace pm {
 int check_opts(const pm_opts& o) {
   if (!(o.tol > 0.0) || o.max_it < 0 || o.replace_every < 1 ||
       (o.precision != PM_FP64 && o.precision != PM_MIXED) || o.tile_rows < 0 || o.block < 0 ||
-      o.iter_shape < -1 || o.iter_shape > 4 ||
+      o.iter_shape < -1 || o.iter_shape > 5 ||
       (o.precond != PM_PREC_JACOBI && o.precond != PM_PREC_CHEBYSHEV) ||
       (o.precond == PM_PREC_CHEBYSHEV && (o.cheb_degree < 2 || o.cheb_degree > 16))) {
     set_error(PM_INVALID_ARG, "invalid solver options");

@@ -37,6 +37,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <iterator>
 #include <map>
 #include <mutex>
 #include <string>
@@ -1157,6 +1158,189 @@ __global__ void __launch_bounds__(512) k_chunk(SetArgs<V, W, I> a, int j0, int j
   }
 }
 
+// Resident window kernel: the form of k_chunk for systems whose operator does
+// not fit on chip (one large tile per compute unit).  What stays in LDS for
+// the whole launch is the tile's column window of p and z; the matrix rows,
+// x_acc and q~ of the tile's own rows are read and written every iteration
+// (each by the one thread that owns the row, so plain loads see its own
+// earlier stores), and the halo exchange, partials and grid barrier are
+// those of k_chunk.  Same arithmetic as k_iter / k_iter_lds, bit for bit.
+// Rows are handled R per thread and trip, R * blockDim rows per trip.
+template <typename V, typename W, typename I>
+__global__ void __launch_bounds__(512) k_chunk_win(SetArgs<V, W, I> a, int j0, int j1,
+                                                   double scale, int max_spins) {
+  constexpr int R = kUnroll;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const int t = xcd_block(blockIdx.x, gridDim.x);
+  SysState& S = a.ss[0];
+  if (S.done) return;
+  const int r0 = a.tile_r0[t], r1 = a.tile_r1[t];
+  const int lo = a.tile_lo[t], nwin = a.tile_hi[t] - lo + 1;
+  const int pub_lo = a.tile_pub_lo[t], pub_hi = a.tile_pub_hi[t];
+  const int nt = gridDim.x;
+  const int B = blockDim.x, tid = threadIdx.x;
+  const size_t N = (size_t)a.N;
+  V* __restrict__ lp = reinterpret_cast<V*>(lds_raw);
+  V* __restrict__ lz = lp + nwin;
+  const int nlow = r0 - lo, nhalo = nwin - (r1 - r0);
+  auto halo_w = [&](int h) { return h < nlow ? h : h + (r1 - r0); };
+  {
+    const int src0 = (j0 - 1) & 1;
+    for (int i = r0 + tid; i < r1; i += B) {
+      lp[i - lo] = a.p[src0][i];
+      lz[i - lo] = a.z[src0][i];
+    }
+  }
+  const bool first_block = t == 0 && tid == 0;
+  double al = 0.0, be = 0.0, rho = 0.0;
+  int k_done = -1;
+  bool failed = false;
+  int src = (j0 - 1) & 1;
+  for (int j = j0; j < j1; ++j, src ^= 1) {
+    const bool first = j == j0, last = j + 1 == j1;
+    if (!first && !grid_barrier(a.flags, t, nt, (uint32_t)(S.iter_base + j - 1), max_spins)) {
+      failed = true;
+      break;
+    }
+    const V* __restrict__ ps = a.p[src];
+    const V* __restrict__ zs = a.z[src];
+    const V* __restrict__ qs = a.q[src];
+    V* __restrict__ pd = a.p[src ^ 1];
+    V* __restrict__ zd = a.z[src ^ 1];
+    V* __restrict__ qd = a.q[src ^ 1];
+    constexpr int HR = 4;
+    V hp[HR], hz[HR], hq[HR];
+#pragma unroll
+    for (int u = 0; u < HR; ++u) {
+      const int h = tid + u * B;
+      const int i = lo + halo_w(h < nhalo ? h : (nhalo > 0 ? nhalo - 1 : 0));
+      const int ic = nhalo > 0 ? i : r0;
+      hp[u] = ld_agent(ps + ic);
+      hz[u] = ld_agent(zs + ic);
+      hq[u] = ld_agent(qs + ic);
+    }
+    double r[4];
+    partial_reduce_agent(a.part[src], nt, r);
+    const int k = S.iter_base + j;
+    const double pq = r[0], rh = r[3];
+    if (const int stop = stop_code(k, S.max_it, pq, rh)) {
+      if (first_block) {
+        S.status = stop == 100 ? PM_OK : stop;
+        S.done = 1;
+      }
+      break;
+    }
+    const double a_ = rh / pq;
+    const double rn = rh - 2.0 * a_ * r[1] + a_ * a_ * r[2];
+    const double b_ = rn / rh;
+    const double as = a_ * scale, bs = b_ * scale;
+    // own rows, R per trip: x_acc += alpha p; new z, p into LDS (published
+    // where another tile's window reaches them)
+    for (int base = r0 + tid; base < r1; base += R * B) {
+      V qo[R], xo[R];
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        const int ir = base + u * B;
+        const int i = ir < r1 ? ir : r0;
+        // a published row was stored device-coherently: read it back so
+        qo[u] = !first && (i < pub_lo || i >= pub_hi) ? ld_agent(qs + i) : qs[i];
+        xo[u] = a.xacc[i];
+      }
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        const int i = base + u * B;
+        if (i >= r1) continue;
+        const int li = i - lo;
+        const V pold = lp[li];
+        const V zn = (V)((double)lz[li] - as * (double)qo[u]);
+        const V pn = (V)((double)zn + bs * (double)pold);
+        a.xacc[i] = (V)((double)xo[u] + as * (double)pold);
+        lp[li] = pn;
+        lz[li] = zn;
+        if (last) {
+          zd[i] = zn;
+          pd[i] = pn;
+        } else if (i < pub_lo || i >= pub_hi) {
+          st_agent(zd + i, zn);
+          st_agent(pd + i, pn);
+        }
+      }
+    }
+    auto stage_halo = [&](int h, V pold, V zold, V qold) {
+      const V zn = (V)((double)zold - as * (double)qold);
+      const V pn = (V)((double)zn + bs * (double)pold);
+      const int w = halo_w(h);
+      lp[w] = pn;
+      lz[w] = zn;
+    };
+#pragma unroll
+    for (int u = 0; u < HR; ++u) {
+      const int h = tid + u * B;
+      if (h < nhalo) stage_halo(h, hp[u], hz[u], hq[u]);
+    }
+    for (int h = tid + HR * B; h < nhalo; h += B) {
+      const int i = lo + halo_w(h);
+      stage_halo(h, ld_agent(ps + i), ld_agent(zs + i), ld_agent(qs + i));
+    }
+    __syncthreads();
+    // product of the new direction for own rows, R per trip
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int base = r0 + tid; base < r1; base += R * B) {
+      W w0[R], w1[R], w2[R], cc[R];
+      I i0[R], i1[R], i2[R];
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        const int ir = base + u * B;
+        const int i = ir < r1 ? ir : r0;
+        w0[u] = a.w[i];
+        w1[u] = a.w[N + i];
+        w2[u] = a.w[2 * N + i];
+        i0[u] = a.idx[i];
+        i1[u] = a.idx[N + i];
+        i2[u] = a.idx[2 * N + i];
+        cc[u] = a.c[i];
+      }
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        const int i = base + u * B;
+        if (i >= r1) continue;
+        const int li = i - lo;
+        const double pi = (double)lp[li], zi = (double)lz[li], ci = (double)cc[u];
+        double y = ci * pi;
+        y += (double)w0[u] * (pi - (double)lp[col_of<I>(i, i0[u]) - lo]);
+        y += (double)w1[u] * (pi - (double)lp[col_of<I>(i, i1[u]) - lo]);
+        y += (double)w2[u] * (pi - (double)lp[col_of<I>(i, i2[u]) - lo]);
+        const double d = ((ci + (double)w0[u]) + (double)w1[u]) + (double)w2[u];
+        const V qn = (V)(y / d);
+        if (!last && (i < pub_lo || i >= pub_hi)) st_agent(qd + i, qn);
+        else qd[i] = qn;
+        const double qq = (double)qn;
+        const double dq = d * qq;
+        acc[0] += pi * dq;
+        acc[1] += zi * dq;
+        acc[2] += qq * dq;
+        acc[3] += d * zi * zi;
+      }
+    }
+    tile_partial_agent(acc, a.part[src ^ 1] + 4 * (size_t)t);
+    al = a_;
+    be = b_;
+    rho = rh;
+    k_done = k;
+  }
+  if (first_block && k_done >= 0) {
+    S.alpha = al;
+    S.beta = be;
+    S.rho = rho;
+    S.iter = k_done;
+  }
+  if (failed && tid == 0) {
+    S.status = PM_HIP_ERROR;
+    S.bar_fail = 1;
+    S.done = 1;
+  }
+}
+
 // Split schedule (the tuner may prefer it where the fused kernel's extra
 // neighbour gathers cost more than the pass it saves): after k_spmv on buffer
 // 0, iteration k = iter_base + j updates x_acc, z and p in place with the
@@ -1711,8 +1895,11 @@ Cheb make_cheb(int degree) {
 struct Launch {
   int tile, block, rows;
 };
-// Launch.rows of the resident chunk kernel (k_chunk)
+// Launch.rows of the resident chunk kernel (k_chunk) and of the resident
+// window kernel (k_chunk_win)
 constexpr int kResident = 4;
+constexpr int kResidentWin = 5;
+inline bool is_resident(int rows) { return rows == kResident || rows == kResidentWin; }
 
 template <typename V, typename W, typename I>
 struct Ops {
@@ -1721,7 +1908,7 @@ struct Ops {
     k_flags_reset<<<(S.n_tiles + 255) / 256, 256, 0, s>>>(S.flags, S.n_tiles);
   }
   static void start(SolveSet& S, const A& a, const pm_opts& o, const Launch& L, hipStream_t s) {
-    if (L.rows == kResident) flags_reset(S, s);
+    if (is_resident(L.rows)) flags_reset(S, s);
     const int checks = o.stag_checks > 0 ? o.stag_checks : 40;
     const long win = (long)checks * o.replace_every;
     k_sys_init<<<(S.n_sys + 63) / 64, 64, 0, s>>>(S.ss, S.n_sys, o.max_it,
@@ -1804,9 +1991,38 @@ struct Ops {
     }
     return (long)per_cu * S.n_cu >= (long)S.n_tiles;
   }
+  // resident window kernel: one system, every tile resident at once, the
+  // column windows' p and z in LDS
+  static size_t win_lds_bytes(const SolveSet& S) { return 2 * sizeof(V) * (size_t)S.win_max; }
+  static bool win_fits(const SolveSet& S, const Launch& L) {
+    if (S.n_sys != 1 || S.n_cu <= 0) return false;
+    const size_t need = win_lds_bytes(S);
+    if (need > (size_t)S.lds_limit) return false;
+    const void* f = (const void*)k_chunk_win<V, W, I>;
+    if (need > 65536 &&
+        hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)need) !=
+            hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, L.block, need) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    return (long)per_cu * S.n_cu >= (long)S.n_tiles;
+  }
+  static bool any_resident_fits(const SolveSet& S, const Launch& L) {
+    return L.rows == kResident ? resident_fits(S, L) : win_fits(S, L);
+  }
   // iterations j0 .. j1-1 of a chunk in one resident launch (buffer (j0-1)&1 in)
   static void resident(SolveSet& S, const A& a, int j0, int j1, const Launch& L, hipStream_t s,
                        double scale) {
+    if (L.rows == kResidentWin) {
+      k_chunk_win<V, W, I><<<S.n_tiles, L.block, win_lds_bytes(S), s>>>(a, j0, j1, scale,
+                                                                       S.resident_spins);
+      return;
+    }
     const size_t lds = resident_lds_bytes(S, L);
     if (resident_rpt(L.tile, L.block) == 4)
       k_chunk<V, W, I, 4><<<S.n_tiles, L.block, lds, s>>>(a, j0, j1, scale, S.resident_spins);
@@ -1816,7 +2032,7 @@ struct Ops {
   static void chunk(SolveSet& S, const A& a, int m, const Launch& L, hipStream_t s) {
     spmv(S, a, L, s);
     int src = 0;
-    if (L.rows == kResident) {
+    if (is_resident(L.rows)) {
       if (m > 1) resident(S, a, 1, m, L, s, 1.0);
       src = (m - 1) & 1;
     } else {
@@ -1897,15 +2113,20 @@ int tune_launch(SolveSet& S, const double* val64, const double* b, double* x, co
   Launch arg = {2048, 256, 0};
   pm_opts ot = o;
   ot.max_it = INT_MAX;
-  for (const Launch& L : kCandidates) {
-    if ((long)L.tile * 2 > (long)S.N && L.tile != kCandidates[0].tile) continue;
+  std::vector<Launch> cands(std::begin(kCandidates), std::end(kCandidates));
+  // the resident window kernel with one tile per compute unit
+  if (S.n_sys == 1 && S.n_cu > 0)
+    cands.push_back({std::max(kMinTile, (S.N + S.n_cu - 1) / S.n_cu), 512, kResidentWin});
+  for (const Launch& L : cands) {
+    if (L.rows != kResidentWin && (long)L.tile * 2 > (long)S.N && L.tile != kCandidates[0].tile)
+      continue;
     if (int r = build_tiles(S, L.tile)) return r;
     if (L.rows == 3 && !Ops<V, W, I>::lds_fits(S)) continue;
-    if (L.rows == kResident && !Ops<V, W, I>::resident_fits(S, L)) continue;
+    if (is_resident(L.rows) && !Ops<V, W, I>::any_resident_fits(S, L)) continue;
     const auto a = make_args<V, W, I>(S, val64, b, x);
     Ops<V, W, I>::start(S, a, ot, L, s);
     Ops<V, W, I>::spmv(S, a, L, s);
-    const bool res = L.rows == kResident;
+    const bool res = is_resident(L.rows);
     // warm caches and clocks (the resident kernel's iteration numbers keep
     // increasing from launch to launch, as in a solve)
     if (res) Ops<V, W, I>::resident(S, a, 1, 5, L, s, 0.0);
@@ -1963,7 +2184,7 @@ int run(SolveSet& S, const double* val64, const double* b, double* x, const pm_o
     set_error(PM_INVALID_ARG, "the tile's column window does not fit the LDS of one block");
     return PM_INVALID_ARG;
   }
-  if (L.rows == kResident && !O::resident_fits(S, L)) {
+  if (is_resident(L.rows) && !O::any_resident_fits(S, L)) {
     set_error(PM_INVALID_ARG,
               "the resident schedule needs one system whose tiles all fit the device at once");
     return PM_INVALID_ARG;
@@ -2040,7 +2261,7 @@ int run(SolveSet& S, const double* val64, const double* b, double* x, const pm_o
   // a resident launch whose grid was not all resident at once (a barrier
   // wait gave up): solve again, from the start, on the streaming schedule
   // with the same tiles, which computes bitwise the same iterations
-  if (L.rows == kResident && fin[0].bar_fail) {
+  if (is_resident(L.rows) && fin[0].bar_fail) {
     const Launch L2 = {L.tile, L.block, O::lds_fits(S) ? 3 : 1};
     if (tuned) {
       std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -2152,12 +2373,12 @@ int time_kernel(SolveSet& S, int which, int n_launch, hipStream_t s, double* ms)
   const auto a = make_args<V, W, I>(S, S.last_val, nullptr, nullptr);
   const Launch L = {S.last_tile, S.last_block, S.last_rows};
   k_timing_state<<<(S.n_sys + 63) / 64, 64, 0, s>>>(S.ss, S.n_sys);
-  if (L.rows == kResident) Ops<V, W, I>::flags_reset(S, s);
+  if (is_resident(L.rows)) Ops<V, W, I>::flags_reset(S, s);
   Ops<V, W, I>::spmv(S, a, L, s);  // partials for the first fused iteration
   PS_HIP(hipEventRecord(S.tev[0], s));
   // the resident kernel is timed as the solve runs it: launches of m - 1
   // iterations (m of the last solve); the time returned is per iteration
-  const bool res = which == 1 && L.rows == kResident;
+  const bool res = which == 1 && is_resident(L.rows);
   const int per = res ? std::max(1, S.g_m - 1) : 1;
   if (res) {
     for (int r = 0; r < n_launch; ++r)

@@ -236,28 +236,34 @@ def test_lds_staged_iteration_is_bitwise_the_gather_one():
 def test_resident_chunk_is_bitwise_the_lds_one():
     """The resident chunk kernel (iter_shape 4: a chunk's m - 1 iterations in
     one launch, the tiles' rows held on chip, a grid barrier between
-    iterations) gives bitwise the solutions and iteration counts of the
-    LDS-staged kernel at the same tiles: both precisions, tiles of 4 and 8
-    rows per thread, chunks of 50, 7, 2 and 1 iterations, and an iteration
-    limit that stops inside a chunk."""
+    iterations) and the resident window kernel (iter_shape 5: only the
+    windows' p and z on chip) give bitwise the solutions and iteration
+    counts of the LDS-staged kernel at the same tiles: both precisions,
+    tiles of 4, 8 and (shape 5) 10 rows per thread, chunks of 50, 7, 2 and 1
+    iterations, and an iteration limit that stops inside a chunk."""
     for name in ("chan", "aniso"):
         c = case(name)
         w = c["w"]
         val = B().assemble_corrector(c["mesh"], B().PM_CP2, c["prm"], w["nu"], w["dt"])["val64"]
         b = torch.tensor(w["rhs"]["cp2"], device=c["dev"])
         for prec in (0, 1):
-            for tile, block in ((1024, 256), (2048, 256), (2048, 512), (512, 128)):
+            for tile, block in ((1024, 256), (2048, 256), (2048, 512), (512, 128), (5000, 512)):
                 for m in (50, 7, 2, 1):
                     kw = dict(precision=prec, tile_rows=tile, block=block, replace_every=m)
                     x3, i3 = B().pcg_solve(c["mesh"], val, b, iter_shape=3, **kw)
-                    x4, i4 = B().pcg_solve(c["mesh"], val, b, iter_shape=4, **kw)
-                    assert i3["status"] == 0 and i4["status"] == 0
-                    assert i3["iters"] == i4["iters"] and torch.equal(x3, x4), (name, prec, tile, block, m)
+                    assert i3["status"] == 0
+                    # shape 4 holds at most 8 rows per thread; shape 5 any tile
+                    for shape in ((4, 5) if tile <= 8 * block else (5,)):
+                        x4, i4 = B().pcg_solve(c["mesh"], val, b, iter_shape=shape, **kw)
+                        assert i4["status"] == 0
+                        assert i3["iters"] == i4["iters"] and torch.equal(x3, x4), (
+                            name, prec, tile, block, m, shape)
             kw = dict(precision=prec, tile_rows=2048, block=256, max_it=73)
             x3, i3 = B().pcg_solve(c["mesh"], val, b, iter_shape=3, **kw)
-            x4, i4 = B().pcg_solve(c["mesh"], val, b, iter_shape=4, **kw)
-            assert i3["status"] == i4["status"] == B().PM_MAXIT
-            assert i3["iters"] == i4["iters"] and torch.equal(x3, x4)
+            for shape in (4, 5):
+                x4, i4 = B().pcg_solve(c["mesh"], val, b, iter_shape=shape, **kw)
+                assert i3["status"] == i4["status"] == B().PM_MAXIT
+                assert i3["iters"] == i4["iters"] and torch.equal(x3, x4)
     # more than eight rows per thread is not a resident shape
     c = case("chan")
     w = c["w"]
@@ -301,7 +307,7 @@ def test_kernel_timing_hook_on_every_schedule():
     b = torch.tensor(w["rhs"]["cp2"], device=c["dev"])
     n = c["geo"]["n"]
     for prec, sv in ((0, 8), (1, 4)):
-        for shape in (-1, 1, 3, 4):
+        for shape in (-1, 1, 3, 4, 5):
             kw = dict(precision=prec, tile_rows=2048, block=256, iter_shape=shape)
             x1, i1 = B().pcg_solve(c["mesh"], val, b, **kw)
             for which, reps in ((0, 20), (1, 4), (2, 5)):
@@ -371,7 +377,8 @@ def test_wide_column_offsets_match_narrow_bitwise():
     b = torch.tensor(w["rhs"]["cp2"], device=c["dev"])
     shapes = [dict(tile_rows=1024, block=256, iter_shape=1), dict(tile_rows=2048, block=256, iter_shape=2),
               dict(tile_rows=2048, block=512, iter_shape=3), dict(tile_rows=1024, block=256, iter_shape=-1),
-              dict(tile_rows=2048, block=256, iter_shape=4), dict(tile_rows=1024, block=256, iter_shape=4)]
+              dict(tile_rows=2048, block=256, iter_shape=4), dict(tile_rows=1024, block=256, iter_shape=4),
+              dict(tile_rows=3000, block=512, iter_shape=5)]
     runs = []
     try:
         for bits in (16, 32):

@@ -133,6 +133,22 @@ def test_channel_1M_resident_chunk_is_bitwise_the_lds_one(precision):
     assert i3["iters"] == i4["iters"] and torch.equal(x3, x4)
 
 
+def test_aniso_channel_4M_resident_window_is_bitwise_the_lds_one():
+    """On the 4M channel in mixed precision (one tile per compute unit) the
+    resident window kernel reproduces the LDS-staged schedule bit for bit."""
+    c = channel_case(552, 3, True)
+    w = c["w"]
+    val = B().assemble_corrector(c["mesh"], KIND["cp2"], c["prm"], w["nu"], w["dt"])["val64"]
+    bt = torch.tensor(w["rhs"]["cp2"], device=c["dev"])
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    kw = dict(precision=1, tile_rows=-(-bt.numel() // n_cu), block=512)
+    x3, i3 = B().pcg_solve(c["mesh"], val, bt, iter_shape=3, **kw)
+    x5, i5 = B().pcg_solve(c["mesh"], val, bt, iter_shape=5, **kw)
+    log(f"4M mixed: LDS {i3['iters']} iterations, resident window {i5['iters']}")
+    assert i3["status"] == 0 and i5["status"] == 0
+    assert i3["iters"] == i5["iters"] and torch.equal(x3, x5)
+
+
 def test_aniso_channel_4M_structure_and_residual():
     c = dict(channel_case(552, 3, True), key=(552, 3, True))
     w = c["w"]
