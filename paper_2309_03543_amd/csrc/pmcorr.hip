@@ -482,8 +482,10 @@ int pcg_solve(pm_mesh* m, const double* val64, const double* b, double* x, const
   pm_opts_default(&o);
   if (opts) o = *opts;
   if (int r = check_opts(o)) return r;
+  set_error(PM_OK, "");
   const int st = set_solve(m->set, val64, b, x, o, info, s);
-  if (st < 0) set_error(st, "pcg_solve stopped with an error status");
+  // keep a reason the driver gave; a status the device reached gets this one
+  if (st < 0 && g_last_status == PM_OK) set_error(st, "pcg_solve stopped with an error status");
   return st;
 }
 
