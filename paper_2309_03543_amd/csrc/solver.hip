@@ -1159,17 +1159,17 @@ __global__ void __launch_bounds__(512) k_chunk(SetArgs<V, W, I> a, int j0, int j
 }
 
 // Resident window kernel: the form of k_chunk for systems whose operator does
-// not fit on chip (one large tile per compute unit).  What stays in LDS for
-// the whole launch is the tile's column window of p and z; the matrix rows,
-// x_acc and q~ of the tile's own rows are read and written every iteration
-// (each by the one thread that owns the row, so plain loads see its own
-// earlier stores), and the halo exchange, partials and grid barrier are
-// those of k_chunk.  Same arithmetic as k_iter / k_iter_lds, bit for bit.
-// Rows are handled R per thread and trip, R * blockDim rows per trip.
-template <typename V, typename W, typename I>
+// not fit on chip (one large tile per compute unit).  What stays on chip for
+// the whole launch is the tile's column window of p and z (LDS) and x_acc
+// and q~ of the thread's own rows (registers, RPT rows per thread); the
+// matrix rows are read every iteration.  The halo exchange, partials and
+// grid barrier are those of k_chunk.  Same arithmetic as k_iter /
+// k_iter_lds, bit for bit.  Rows are handled R per trip, RPT / R trips.
+template <typename V, typename W, typename I, int RPT>
 __global__ void __launch_bounds__(512) k_chunk_win(SetArgs<V, W, I> a, int j0, int j1,
                                                    double scale, int max_spins) {
   constexpr int R = kUnroll;
+  static_assert(RPT % R == 0, "rows per thread in whole trips");
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const int t = xcd_block(blockIdx.x, gridDim.x);
   SysState& S = a.ss[0];
@@ -1184,11 +1184,19 @@ __global__ void __launch_bounds__(512) k_chunk_win(SetArgs<V, W, I> a, int j0, i
   V* __restrict__ lz = lp + nwin;
   const int nlow = r0 - lo, nhalo = nwin - (r1 - r0);
   auto halo_w = [&](int h) { return h < nlow ? h : h + (r1 - r0); };
+  V xa[RPT], qo[RPT];
   {
     const int src0 = (j0 - 1) & 1;
-    for (int i = r0 + tid; i < r1; i += B) {
-      lp[i - lo] = a.p[src0][i];
-      lz[i - lo] = a.z[src0][i];
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+      const int ir = r0 + tid + u * B;
+      const int i = ir < r1 ? ir : r0;
+      xa[u] = a.xacc[i];
+      qo[u] = a.q[src0][i];
+      if (ir < r1) {
+        lp[i - lo] = a.p[src0][i];
+        lz[i - lo] = a.z[src0][i];
+      }
     }
   }
   const bool first_block = t == 0 && tid == 0;
@@ -1208,6 +1216,11 @@ __global__ void __launch_bounds__(512) k_chunk_win(SetArgs<V, W, I> a, int j0, i
     V* __restrict__ pd = a.p[src ^ 1];
     V* __restrict__ zd = a.z[src ^ 1];
     V* __restrict__ qd = a.q[src ^ 1];
+    // the first own row, opaque to the compiler in every iteration: the
+    // rows' addresses are then formed again each iteration instead of being
+    // kept live across all of them (RPT rows x every array)
+    int ib = r0 + tid;
+    asm volatile("" : "+v"(ib));
     constexpr int HR = 4;
     V hp[HR], hz[HR], hq[HR];
 #pragma unroll
@@ -1234,36 +1247,25 @@ __global__ void __launch_bounds__(512) k_chunk_win(SetArgs<V, W, I> a, int j0, i
     const double rn = rh - 2.0 * a_ * r[1] + a_ * a_ * r[2];
     const double b_ = rn / rh;
     const double as = a_ * scale, bs = b_ * scale;
-    // own rows, R per trip: x_acc += alpha p; new z, p into LDS (published
-    // where another tile's window reaches them)
-    for (int base = r0 + tid; base < r1; base += R * B) {
-      V qo[R], xo[R];
+    // own rows: x_acc += alpha p; new z, p into LDS (published where another
+    // tile's window reaches them)
 #pragma unroll
-      for (int u = 0; u < R; ++u) {
-        const int ir = base + u * B;
-        const int i = ir < r1 ? ir : r0;
-        // a published row was stored device-coherently: read it back so
-        qo[u] = !first && (i < pub_lo || i >= pub_hi) ? ld_agent(qs + i) : qs[i];
-        xo[u] = a.xacc[i];
-      }
-#pragma unroll
-      for (int u = 0; u < R; ++u) {
-        const int i = base + u * B;
-        if (i >= r1) continue;
-        const int li = i - lo;
-        const V pold = lp[li];
-        const V zn = (V)((double)lz[li] - as * (double)qo[u]);
-        const V pn = (V)((double)zn + bs * (double)pold);
-        a.xacc[i] = (V)((double)xo[u] + as * (double)pold);
-        lp[li] = pn;
-        lz[li] = zn;
-        if (last) {
-          zd[i] = zn;
-          pd[i] = pn;
-        } else if (i < pub_lo || i >= pub_hi) {
-          st_agent(zd + i, zn);
-          st_agent(pd + i, pn);
-        }
+    for (int u = 0; u < RPT; ++u) {
+      const int i = ib + u * B;
+      if (i >= r1) continue;
+      const int li = i - lo;
+      const V pold = lp[li];
+      const V zn = (V)((double)lz[li] - as * (double)qo[u]);
+      const V pn = (V)((double)zn + bs * (double)pold);
+      xa[u] = (V)((double)xa[u] + as * (double)pold);
+      lp[li] = pn;
+      lz[li] = zn;
+      if (last) {
+        zd[i] = zn;
+        pd[i] = pn;
+      } else if (i < pub_lo || i >= pub_hi) {
+        st_agent(zd + i, zn);
+        st_agent(pd + i, pn);
       }
     }
     auto stage_halo = [&](int h, V pold, V zold, V qold) {
@@ -1283,14 +1285,15 @@ __global__ void __launch_bounds__(512) k_chunk_win(SetArgs<V, W, I> a, int j0, i
       stage_halo(h, ld_agent(ps + i), ld_agent(zs + i), ld_agent(qs + i));
     }
     __syncthreads();
-    // product of the new direction for own rows, R per trip
+    // product of the new direction for own rows, R rows per trip
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int base = r0 + tid; base < r1; base += R * B) {
+#pragma unroll
+    for (int tr = 0; tr < RPT / R; ++tr) {
       W w0[R], w1[R], w2[R], cc[R];
       I i0[R], i1[R], i2[R];
 #pragma unroll
       for (int u = 0; u < R; ++u) {
-        const int ir = base + u * B;
+        const int ir = ib + (tr * R + u) * B;
         const int i = ir < r1 ? ir : r0;
         w0[u] = a.w[i];
         w1[u] = a.w[N + i];
@@ -1302,7 +1305,7 @@ __global__ void __launch_bounds__(512) k_chunk_win(SetArgs<V, W, I> a, int j0, i
       }
 #pragma unroll
       for (int u = 0; u < R; ++u) {
-        const int i = base + u * B;
+        const int i = ib + (tr * R + u) * B;
         if (i >= r1) continue;
         const int li = i - lo;
         const double pi = (double)lp[li], zi = (double)lz[li], ci = (double)cc[u];
@@ -1312,8 +1315,9 @@ __global__ void __launch_bounds__(512) k_chunk_win(SetArgs<V, W, I> a, int j0, i
         y += (double)w2[u] * (pi - (double)lp[col_of<I>(i, i2[u]) - lo]);
         const double d = ((ci + (double)w0[u]) + (double)w1[u]) + (double)w2[u];
         const V qn = (V)(y / d);
-        if (!last && (i < pub_lo || i >= pub_hi)) st_agent(qd + i, qn);
-        else qd[i] = qn;
+        qo[tr * R + u] = qn;
+        if (last) qd[i] = qn;
+        else if (i < pub_lo || i >= pub_hi) st_agent(qd + i, qn);
         const double qq = (double)qn;
         const double dq = d * qq;
         acc[0] += pi * dq;
@@ -1327,6 +1331,12 @@ __global__ void __launch_bounds__(512) k_chunk_win(SetArgs<V, W, I> a, int j0, i
     be = b_;
     rho = rh;
     k_done = k;
+  }
+  // x_acc of the completed iterations
+#pragma unroll
+  for (int u = 0; u < RPT; ++u) {
+    const int i = r0 + tid + u * B;
+    if (i < r1) a.xacc[i] = xa[u];
   }
   if (first_block && k_done >= 0) {
     S.alpha = al;
@@ -1994,11 +2004,21 @@ struct Ops {
   // resident window kernel: one system, every tile resident at once, the
   // column windows' p and z in LDS
   static size_t win_lds_bytes(const SolveSet& S) { return 2 * sizeof(V) * (size_t)S.win_max; }
+  // rows per thread of the resident window kernel: 8, 16 or 32 (0: too many)
+  static int win_rpt(int tile, int block) {
+    return tile <= 8 * block ? 8 : tile <= 16 * block ? 16 : tile <= 32 * block ? 32 : 0;
+  }
+  static const void* win_fn(int rpt) {
+    return rpt == 8    ? (const void*)k_chunk_win<V, W, I, 8>
+           : rpt == 16 ? (const void*)k_chunk_win<V, W, I, 16>
+                       : (const void*)k_chunk_win<V, W, I, 32>;
+  }
   static bool win_fits(const SolveSet& S, const Launch& L) {
-    if (S.n_sys != 1 || S.n_cu <= 0) return false;
+    const int rpt = win_rpt(L.tile, L.block);
+    if (S.n_sys != 1 || S.n_cu <= 0 || rpt == 0) return false;
     const size_t need = win_lds_bytes(S);
     if (need > (size_t)S.lds_limit) return false;
-    const void* f = (const void*)k_chunk_win<V, W, I>;
+    const void* f = win_fn(rpt);
     if (need > 65536 &&
         hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)need) !=
             hipSuccess) {
@@ -2019,8 +2039,19 @@ struct Ops {
   static void resident(SolveSet& S, const A& a, int j0, int j1, const Launch& L, hipStream_t s,
                        double scale) {
     if (L.rows == kResidentWin) {
-      k_chunk_win<V, W, I><<<S.n_tiles, L.block, win_lds_bytes(S), s>>>(a, j0, j1, scale,
-                                                                       S.resident_spins);
+      const size_t lds = win_lds_bytes(S);
+      const int sp = S.resident_spins;
+      switch (win_rpt(L.tile, L.block)) {
+        case 8:
+          k_chunk_win<V, W, I, 8><<<S.n_tiles, L.block, lds, s>>>(a, j0, j1, scale, sp);
+          break;
+        case 16:
+          k_chunk_win<V, W, I, 16><<<S.n_tiles, L.block, lds, s>>>(a, j0, j1, scale, sp);
+          break;
+        default:
+          k_chunk_win<V, W, I, 32><<<S.n_tiles, L.block, lds, s>>>(a, j0, j1, scale, sp);
+          break;
+      }
       return;
     }
     const size_t lds = resident_lds_bytes(S, L);
