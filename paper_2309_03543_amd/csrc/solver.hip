@@ -15,12 +15,14 @@
 // (k_update_flush), an exact float64 residual from the CSR matrix (k_resid,
 // k_sys_check) and the new direction (k_pdir).  Between them the per-iteration
 // kernels synchronise only through kernel boundaries: no fences, no spin
-// waits.  Where every tile of one system fits the device at once, the
-// resident chunk kernel (k_chunk) instead runs the chunk's m - 1 iterations
-// in one launch, holding each tile's rows on chip and separating iterations
-// with a bounded grid barrier on per-tile flags.  Chunks are captured once in
-// a HIP graph and replayed; a system whose test passes is masked out of later
-// kernels.
+// waits.  Where every tile of one system fits the device at once, a
+// resident kernel instead runs the chunk's m - 1 iterations in one launch,
+// separating iterations with a bounded grid barrier on per-tile flags:
+// k_chunk holds each tile's rows (matrix and vectors) on chip; k_chunk_win,
+// for larger operators, one tile per compute unit, holds the tile's column
+// window of p and z and its rows' x_acc and q~, and streams the matrix.
+// Chunks are captured once in a HIP graph and replayed; a system whose test
+// passes is masked out of later kernels.
 //
 // Difference form: row i is stored as c_i = sum_j a_ij (its mass or
 // Dirichlet part) and w_ij = -a_ij, and (A p)_i = c_i p_i + sum_j w_ij (p_i -
