@@ -277,23 +277,25 @@ def test_resident_chunk_is_bitwise_the_lds_one():
 
 
 def test_resident_barrier_that_gives_up_falls_back_to_streaming(monkeypatch):
-    """With the barrier's wait bound set to zero polls every wait of the
-    resident kernel gives up (each block then exits normally); the solve is
-    redone on the LDS schedule with the same tiles and matches it bitwise."""
+    """With the barrier's wait bound set to zero polls every wait of a
+    resident kernel (schedules 4 and 5) gives up, each block then exiting
+    normally; the solve is redone on the LDS schedule with the same tiles and
+    matches it bitwise."""
     c = case("chan")
     w = c["w"]
     val = B().assemble_corrector(c["mesh"], B().PM_CP2, c["prm"], w["nu"], w["dt"])["val64"]
     b = torch.tensor(w["rhs"]["cp2"], device=c["dev"])
     kw = dict(tile_rows=2048, block=256)
     x3, i3 = B().pcg_solve(c["mesh"], val, b, iter_shape=3, **kw)
-    monkeypatch.setenv("PMCORR_RESIDENT_SPINS", "0")
-    x4, i4 = B().pcg_solve(c["mesh"], val, b, iter_shape=4, **kw)
-    assert i4["status"] == 0 and i4["iters"] == i3["iters"] and torch.equal(x3, x4)
-    assert B().pm_last_launch(c["mesh"])["iter_shape"] == 3
-    monkeypatch.delenv("PMCORR_RESIDENT_SPINS")
-    x5, i5 = B().pcg_solve(c["mesh"], val, b, iter_shape=4, **kw)
-    assert B().pm_last_launch(c["mesh"])["iter_shape"] == 4
-    assert i5["iters"] == i3["iters"] and torch.equal(x3, x5)
+    for shape in (4, 5):
+        monkeypatch.setenv("PMCORR_RESIDENT_SPINS", "0")
+        x4, i4 = B().pcg_solve(c["mesh"], val, b, iter_shape=shape, **kw)
+        assert i4["status"] == 0 and i4["iters"] == i3["iters"] and torch.equal(x3, x4)
+        assert B().pm_last_launch(c["mesh"])["iter_shape"] == 3
+        monkeypatch.delenv("PMCORR_RESIDENT_SPINS")
+        x5, i5 = B().pcg_solve(c["mesh"], val, b, iter_shape=shape, **kw)
+        assert B().pm_last_launch(c["mesh"])["iter_shape"] == shape
+        assert i5["iters"] == i3["iters"] and torch.equal(x3, x5)
 
 
 def test_kernel_timing_hook_on_every_schedule():
