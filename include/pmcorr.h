@@ -270,7 +270,13 @@ int assemble_corrector(pm_mesh* mesh, int32_t kind, const pm_cell_params* params
  *          opts->x0_is_zero), solution out
  *   opts   host, nullable (defaults); info host out, nullable
  * Returns info->status (PM_OK, PM_MAXIT, PM_STAGNATED, PM_BREAKDOWN) or an
- * error.
+ * error.  PM_OK always means the float64 test passed.  A breakdown
+ * (p.Ap <= 0 or not finite) whose returned x passes the test is PM_OK.  CG
+ * ends within n iterations, so on a system of a few rows p.Ap reaches zero
+ * before the next test.  A recurrence that reaches an exactly zero residual,
+ * or breaks down after progress, while the test fails (float32 storage on
+ * such a system) goes on from the returned x, at most four more passes;
+ * info->iters counts all of them.
  */
 int pcg_solve(pm_mesh* mesh, const double* val64, const double* b, double* x, const pm_opts* opts,
               pm_info* info, hipStream_t stream);

@@ -173,4 +173,6 @@ def coupled_pcg(A_x, A_y, m_perm, b_x, b_y, tol=1e-10, max_it=100000, check_ever
     info["rel_res_true"] = float(np.linalg.norm(b - C @ x)) / bnorm
     if info["status"] == opcg.OK:
         info["status"] = opcg.MAXIT
+    elif info["status"] == opcg.BREAKDOWN and info["rel_res_true"] <= tol:
+        info["status"] = opcg.OK  # converged before p.q reached zero, as in pcg()
     return (x[:n], x[n:]), info

@@ -193,6 +193,11 @@ def pcg(A, b, tol=1e-10, max_it=100000, replace_every=50, x0=None, record=False,
     info["rel_res_true"] = float(np.linalg.norm(true_residual(A, b, x))) / bnorm
     if info["status"] == OK:
         info["status"] = MAXIT
+    elif info["status"] == BREAKDOWN and info["rel_res_true"] <= tol:
+        # CG ends within n iterations in exact arithmetic; on a system of a few
+        # rows the recursion then decays to p.q = 0 before the next convergence
+        # test.  An iterate that meets the tolerance is a converged solve.
+        info["status"] = OK
     return x, info
 
 

@@ -436,12 +436,14 @@ int run(const CoupledIn& in, CoupledWork& w, CA<T>& a, double tol, int max_it, i
       double r2 = 0.0;
       if (int r = fetch_sum(a, w.h_part, s, &r2, &flag)) return r;
       rel = std::sqrt(r2) / res.bnorm;
-      if (flag == kFlagBreakdown) {
-        status = PM_BREAKDOWN;
-        break;
-      }
+      // a breakdown on an iterate that meets the tolerance is convergence
+      // (a system of a few rows: CG has ended, then p.q decays to zero)
       if (rel <= tol) {
         status = PM_OK;
+        break;
+      }
+      if (flag == kFlagBreakdown) {
+        status = PM_BREAKDOWN;
         break;
       }
     }

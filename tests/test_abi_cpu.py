@@ -100,6 +100,7 @@ def test_hand_graph_orders_through_a_mesh():
         (np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]]), np.array([[0, 2, 1]]), B.PM_BAD_MESH),
         (np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]]), np.array([[0, 1, 1]]), B.PM_BAD_MESH),
         (np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]]), np.array([[0, 1, 3]]), B.PM_INVALID_ARG),
+        (np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]]), np.zeros((0, 3), np.int64), B.PM_INVALID_ARG),
         (np.array([[0.0, 0.0], [1.0, np.inf], [0.0, 1.0]]), np.array([[0, 1, 2]]), B.PM_NONFINITE),
         (np.array([[0.0, 0.0], [1.0, 0.0], [1.0, 1.0], [0.0, 1.0]]), np.array([[0, 1, 2], [0, 2, 3]]),
          B.PM_NOT_DELAUNAY),

@@ -323,6 +323,51 @@ def test_kernel_timing_hook_on_every_schedule():
             assert torch.equal(x1, x2) and i1["iters"] == i2["iters"]
 
 
+@functools.lru_cache(maxsize=None)
+def few_cells(n_cells):
+    """One equilateral triangle, or two forming a rhombus; every boundary side
+    is a Dirichlet side of both problems; per-cell parameters of the small
+    inclusion workload."""
+    h = math.sqrt(3.0) / 2
+    xy = np.array([[0.0, 0.0], [1.0, 0.0], [0.5, h], [1.5, h]])[: n_cells + 2]
+    tri = np.array([[0, 1, 2], [1, 3, 2]])[:n_cells]
+    interior = geometry.build(xy, tri, np.zeros((n_cells, 3), np.int8))["interior"]
+    tag = np.where(interior, 0, 3).astype(np.int8)
+    geo = geometry.build(xy, tri, tag)
+    w = workloads.square_inclusion(npts=5, seed=2)
+    params = {k: np.ascontiguousarray(v[:n_cells]) for k, v in w["params"].items()}
+    dev = torch.device("cuda:0")
+    return {"geo": geo, "perm": ordering.rcm(geo["nbr"]), "mesh": B().Mesh(xy, tri, tag),
+            "params": params, "prm": {k: torch.tensor(v, device=dev) for k, v in params.items()},
+            "nu": w["nu"], "dt": w["dt"], "dev": dev}
+
+
+@pytest.mark.parametrize("n_cells", [1, 2])
+@pytest.mark.parametrize("kind", ["cp1x", "cp2"])
+def test_one_and_two_cell_systems(n_cells, kind):
+    """The smallest meshes: assembly to the oracle's values, and every schedule
+    in both precisions converges (CG ends within n iterations, before the
+    first convergence test) to the oracle's solution."""
+    c = few_cells(n_cells)
+    A = oasm.assemble(c["geo"], c["perm"], KIND[kind], c["params"], c["nu"], c["dt"])["A"]
+    val = B().assemble_corrector(c["mesh"], KIND[kind], c["prm"], c["nu"], c["dt"])["val64"]
+    assert np.all(np.abs(val.cpu().numpy() - A.data) <= 1e-13 * np.abs(A.data))
+    b = np.random.default_rng(n_cells).standard_normal(n_cells)
+    bp = b[c["perm"]]
+    xo, io = opcg.pcg(A, bp, tol=1e-10)
+    assert io["status"] == opcg.OK
+    bt = torch.tensor(b, device=c["dev"])
+    shapes = [{}] + [dict(tile_rows=256, block=256, iter_shape=s) for s in (-1, 0, 1, 2, 3, 4, 5)]
+    for prec in (0, 1):
+        for shape in shapes:
+            print(f"== cells {n_cells} {kind} precision {prec} {shape}", flush=True)
+            x, info = B().pcg_solve(c["mesh"], val, bt, precision=prec, **shape)
+            xg = x.cpu().numpy()[c["perm"]]
+            assert info["status"] == 0
+            assert opcg.rel_residual(A, bp, xg) <= 1e-10
+            assert np.linalg.norm(xg - xo) <= 1e-9 * np.linalg.norm(xo)
+
+
 def test_error_statuses():
     Bm = B()
     c = case("tiny")

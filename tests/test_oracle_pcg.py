@@ -58,9 +58,29 @@ def test_statuses():
     xs, _ = pcg.pcg(A, b, tol=1e-10)
     x, info = pcg.pcg(A, b, tol=1e-9, x0=xs)
     assert info["iters"] == 0 and info["status"] == pcg.OK
+    # p.q = 0 at the first step, far from the solution: a breakdown
+    indef = sp.csr_matrix(np.diag([1.0, -1.0]))
+    x, info = pcg.pcg(indef, np.array([1.0, 1.0]))
+    assert info["status"] == pcg.BREAKDOWN and info["iters"] == 0
+    # three rows, indefinite: CG ends within three steps, then p.q reaches 0
+    # on an iterate that solves the system, which is convergence
     indef = sp.csr_matrix(np.diag([1.0, -1.0, 2.0]))
     x, info = pcg.pcg(indef, np.array([1.0, 1.0, 1.0]))
-    assert info["status"] == pcg.BREAKDOWN
+    assert info["status"] == pcg.OK and np.allclose(x, [1.0, -1.0, 0.5], rtol=0, atol=1e-15)
+
+
+def test_systems_of_one_and_two_rows_converge():
+    """CG solves an n-row system within n iterations.  On one and two rows the
+    recursion then reaches p.q = 0 before the first convergence test; the
+    iterate, which meets the tolerance, is a converged solve (pinned against
+    the direct solution), and a breakdown far from the solution stays one."""
+    for A in (sp.csr_matrix([[4.0]]), sp.csr_matrix([[5.0, -1.0], [-1.0, 3.0]])):
+        b = np.arange(1.0, A.shape[0] + 1.0)
+        x, info = pcg.pcg(A, b, tol=1e-10)
+        assert info["status"] == pcg.OK and 1 <= info["iters"] < 50
+        xd = np.linalg.solve(A.toarray(), b)
+        assert np.linalg.norm(x - xd) <= 1e-13 * np.linalg.norm(xd)
+        assert info["rel_res_true"] <= 1e-15
 
 
 def test_two_sum_is_error_free():
