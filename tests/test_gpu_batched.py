@@ -127,3 +127,57 @@ def test_batched_chebyshev_matches_single_solves():
             assert opcg.rel_residual(A, bo, xg) <= 1e-10
             ref = x1.cpu().numpy()[perm]
             assert np.linalg.norm(xg - ref) <= 1e-9 * np.linalg.norm(ref)
+
+
+def few_cell_system(n_cells, dev):
+    """One equilateral triangle, or two forming a rhombus, with every boundary
+    side a Dirichlet side; per-cell parameters of the small inclusion
+    workload.  Returns the mesh, matrix, right-hand side and oracle data."""
+    import math
+
+    h = math.sqrt(3.0) / 2
+    xy = np.array([[0.0, 0.0], [1.0, 0.0], [0.5, h], [1.5, h]])[: n_cells + 2]
+    tri = np.array([[0, 1, 2], [1, 3, 2]])[:n_cells]
+    interior = geometry.build(xy, tri, np.zeros((n_cells, 3), np.int8))["interior"]
+    tag = np.where(interior, 0, 3).astype(np.int8)
+    geo = geometry.build(xy, tri, tag)
+    perm = ordering.rcm(geo["nbr"])
+    w = workloads.square_inclusion(npts=5, seed=2)
+    params = {k: np.ascontiguousarray(v[:n_cells]) for k, v in w["params"].items()}
+    mesh = B().Mesh(xy, tri, tag)
+    prm = {k: torch.tensor(v, device=dev) for k, v in params.items()}
+    val = B().assemble_corrector(mesh, B().PM_CP2, prm, w["nu"], w["dt"])["val64"]
+    b = np.random.default_rng(7 + n_cells).standard_normal(n_cells)
+    A = oasm.assemble(geo, perm, oasm.CP2, params, w["nu"], w["dt"])["A"]
+    return mesh, val, torch.tensor(b, device=dev), (perm, A, b[perm])
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_with_one_and_two_cell_systems(precision):
+    """A 1-cell, a larger and a 2-cell system in one batch.  The small systems
+    end their recursion before the first convergence test (a zero residual or
+    p.q = 0), and in float32 storage are solved on from their iterate; the
+    larger one is unaffected.  Each matches its single solve and the oracle."""
+    dev = torch.device("cuda:0")
+    big = batch_case()
+    parts = [few_cell_system(1, dev),
+             (big["meshes"][0], big["vals"][0], big["bs"][0], big["oracle"][0]),
+             few_cell_system(2, dev)]
+    batch = B().Batch([p[0] for p in parts])
+    val = torch.cat([p[1] for p in parts])
+    b = torch.cat([p[2] for p in parts])
+    x, infos = B().pcg_solve_batched(batch, val, b, precision=precision)
+    torch.cuda.synchronize()
+    for s, (mesh, v, bs, (perm, A, bo)) in enumerate(parts):
+        info = infos[s]
+        xg = x[batch.vec_off[s]: batch.vec_off[s + 1]].cpu().numpy()[perm]
+        assert info["status"] == 0
+        assert opcg.rel_residual(A, bo, xg) <= 1e-10
+        x1, i1 = B().pcg_solve(mesh, v, bs, precision=precision)
+        assert i1["status"] == 0
+        ref = x1.cpu().numpy()[perm]
+        assert np.linalg.norm(xg - ref) <= 1e-9 * np.linalg.norm(ref)
+        if precision == 0:
+            xo, io = opcg.pcg(A, bo, tol=1e-10)
+            assert io["status"] == opcg.OK
+            assert np.linalg.norm(xg - xo) <= 1e-9 * np.linalg.norm(xo)
