@@ -440,8 +440,11 @@ int cp1_solve_coupled(pm_mesh* mesh, const pm_cell_params* params, double nu, do
  *   info            host out, nullable: iterations, status, the true
  *                   relative residual of (u, v) and ||b||
  * Errors: PM_INVALID_ARG (arguments, off-diagonals that differ, a cell
- * block that is not positive definite), PM_NONFINITE, PM_BREAKDOWN.  The
- * first call on a mesh allocates a workspace of 13 n doubles, and the first
+ * block that is not positive definite), PM_NONFINITE, PM_BREAKDOWN.  A
+ * breakdown (p.q <= 0) after (u, v) met the tolerance is PM_OK.  With
+ * PM_MIXED on a mesh of a few cells, the float32 recurrence can reach
+ * p.q = 0 before the float64 test passes.  There is no restart, so that
+ * case is PM_BREAKDOWN.  The first call on a mesh allocates a workspace of 13 n doubles, and the first
  * call of each precision 13 n doubles (float64) or 19 n floats (mixed) more,
  * kept until pm_mesh_destroy.
  */

@@ -444,6 +444,7 @@ int run(const CoupledIn& in, CoupledWork& w, CA<T>& a, double tol, int max_it, i
       }
       if (flag == kFlagBreakdown) {
         status = PM_BREAKDOWN;
+        set_error(status, "coupled CP1: p.q <= 0 or not finite before the tolerance was met");
         break;
       }
     }

@@ -261,3 +261,59 @@ def test_coupled_pcg_is_the_limit_of_the_loop():
                                         toll=0.0, max_outer=passes)
         errs.append((torch.linalg.norm(torch.cat([u, v]) - xc) / torch.linalg.norm(xc)).item())
     assert errs[0] > errs[1] > errs[2] and errs[2] < 1e-6
+
+
+def few_case(n_cells):
+    """One equilateral triangle, or two forming a rhombus, every boundary side
+    a Dirichlet side; anisotropic cells (ratio 100 at 30 degrees)."""
+    h = math.sqrt(3.0) / 2
+    xy = np.array([[0.0, 0.0], [1.0, 0.0], [0.5, h], [1.5, h]])[: n_cells + 2]
+    tri = np.array([[0, 1, 2], [1, 3, 2]])[:n_cells]
+    interior = geometry.build(xy, tri, np.zeros((n_cells, 3), np.int8))["interior"]
+    tag = np.where(interior, 0, 3).astype(np.int8)
+    a, b, d = fields.aniso_shape(100.0, math.radians(30.0))
+    K, eps0 = 1e-4, 0.35
+    prm = {"eps": np.full(n_cells, eps0), "logk": np.full(n_cells, math.log(K)),
+           "chi": np.full(n_cells, 0.7), "g11": np.full(n_cells, a), "g12": np.full(n_cells, b),
+           "g22": np.full(n_cells, d)}
+    dt = 0.05 * K / (NU * eps0)
+    geo = geometry.build(xy, tri, tag)
+    perm = ordering.rcm(geo["nbr"])
+    Ax = oasm.assemble(geo, perm, oasm.CP1X, prm, NU, dt)["A"]
+    Ay = oasm.assemble(geo, perm, oasm.CP1Y, prm, NU, dt)["A"]
+    mesh = B().Mesh(xy, tri, tag)
+    dev = torch.device("cuda:0")
+    tprm = {k: torch.tensor(v, device=dev) for k, v in prm.items()}
+    vx = B().assemble_corrector(mesh, B().PM_CP1X, tprm, NU, dt)["val64"]
+    vy = B().assemble_corrector(mesh, B().PM_CP1Y, tprm, NU, dt)["val64"]
+    rng = np.random.default_rng(20 + n_cells)
+    return {"geo": geo, "perm": perm, "prm": prm, "tprm": tprm, "dt": dt, "Ax": Ax, "Ay": Ay,
+            "mesh": mesh, "vx": vx, "vy": vy, "bx": rng.standard_normal(n_cells),
+            "by": rng.standard_normal(n_cells), "dev": dev, "n": n_cells}
+
+
+@pytest.mark.parametrize("n_cells", [1, 2])
+def test_coupled_pcg_on_one_and_two_cells(n_cells):
+    """CG ends within 2n iterations, before the first convergence test, and
+    p.q then decays to zero: float64 reports convergence to the oracle's
+    solution.  Float32 storage has no restart after such a breakdown, so it may
+    report PM_BREAKDOWN, but never PM_OK without meeting the tolerance."""
+    c = few_case(n_cells)
+    (uo, vo, io), (u, v, info), m = pcg_both(c)
+    assert info["status"] == 0 and io["status"] == 0
+    perm = c["perm"]
+    C = occ.coupled_matrix(c["Ax"], c["Ay"], m)
+    b = np.concatenate([c["bx"][perm], c["by"][perm]])
+    x = np.concatenate([u[perm], v[perm]])
+    assert np.linalg.norm(b - C @ x) <= 1e-10 * np.linalg.norm(b)
+    xo = np.concatenate([uo, vo])
+    assert np.linalg.norm(np.concatenate([u, v]) - xo) <= 1e-9 * np.linalg.norm(xo)
+    try:
+        _, (u, v, info), _ = pcg_both(c, precision=1)
+    except B().PMError as e:
+        assert e.status == B().PM_BREAKDOWN and "p.q" in str(e)
+        print(f"mixed coupled CG, {n_cells} cells: breakdown", flush=True)
+    else:
+        assert info["status"] == 0
+        x = np.concatenate([u[perm], v[perm]])
+        assert np.linalg.norm(b - C @ x) <= 1e-10 * np.linalg.norm(b)
